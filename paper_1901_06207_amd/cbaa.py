@@ -1,0 +1,343 @@
+"""Python binding of libcbaa (ctypes). Argument marshalling only: every step of
+the detector runs in the library's HIP kernels; PyTorch provides device
+memory and streams.
+
+The functions named ``cbaa_*`` mirror the C ABI of ``include/cbaa.h`` one to
+one (tensors in place of device pointers, ``stream=None`` meaning torch's
+current stream). A few conveniences (``new_cube``, ``restore``, ``estimate``)
+allocate buffers with torch and call those.
+
+Loading fails loudly when the built library is missing: there is no fallback.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import dataclasses
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libcbaa.so")
+
+CBAA_OK, CBAA_EINVAL, CBAA_ECONFIG, CBAA_ESCRATCH, CBAA_EHIP = 0, -1, -2, -3, -4
+SIDE_SRC, SIDE_DST = 0, 1
+THR_THM2, THR_PAPER = 0, 1
+FLAG_SATURATED = 1
+MAX_RA, MAX_VA = 4, 2
+
+
+class CbaaError(RuntimeError):
+    def __init__(self, code: int, where: str, detail: str):
+        super().__init__(f"{where}: {detail} (code {code})")
+        self.code = code
+
+
+class cbaa_config(C.Structure):
+    _fields_ = [("r", C.c_uint32), ("n_ra", C.c_uint32), ("n_va", C.c_uint32),
+                ("log2_g", C.c_uint32), ("cbn", C.c_uint32 * 6), ("cl_bs", C.c_uint32 * 4),
+                ("seed_mangle", C.c_uint32), ("seed_bv", C.c_uint32),
+                ("seed_va", C.c_uint32 * 2)]
+
+
+class cbaa_restore_stats(C.Structure):
+    _fields_ = [("n_hosts", C.c_uint64), ("hot_columns", C.c_uint64),
+                ("partial_checked", C.c_uint64), ("tuples_checked", C.c_uint64)]
+
+
+HOST_DTYPE = np.dtype([("ip", "<u4"), ("zeros", "<u2"), ("cs", "u1"), ("flags", "u1"),
+                       ("est", "<f8")])
+HOST_BYTES = 16
+
+
+@dataclasses.dataclass(frozen=True)
+class Config:
+    """Detector configuration (fields of cbaa_config)."""
+
+    r: int = 4
+    n_ra: int = 3
+    n_va: int = 1
+    log2_g: int = 12
+    cbn: tuple = (12, 12, 12, 12)
+    cl_bs: tuple = (4, 14, 23)
+    seed_mangle: int = 0x243F6A88
+    seed_bv: int = 0x85A308D3
+    seed_va: tuple = (0x13198A2E, 0x03707344)
+
+    @classmethod
+    def from_dict(cls, p: dict) -> "Config":
+        return cls(r=p["r"], n_ra=p["n_ra"], n_va=p["n_va"], log2_g=p["log2_g"],
+                   cbn=tuple(p["cbn"]), cl_bs=tuple(p["cl_bs"]), seed_mangle=p["seed_mangle"],
+                   seed_bv=p["seed_bv"], seed_va=tuple(p["seed_va"]))
+
+    def to_c(self) -> cbaa_config:
+        c = cbaa_config()
+        c.r, c.n_ra, c.n_va, c.log2_g = self.r, self.n_ra, self.n_va, self.log2_g
+        for i, v in enumerate(self.cbn):
+            c.cbn[i] = v
+        for i, v in enumerate(self.cl_bs):
+            c.cl_bs[i] = v
+        c.seed_mangle, c.seed_bv = self.seed_mangle, self.seed_bv
+        for i, v in enumerate(self.seed_va):
+            c.seed_va[i] = v
+        return c
+
+    @property
+    def n_arrays(self) -> int:
+        return self.n_ra + self.n_va
+
+    @property
+    def g(self) -> int:
+        return 1 << self.log2_g
+
+    @property
+    def n_sketches(self) -> int:
+        return 1 << self.r
+
+    @property
+    def slab_words(self) -> int:
+        return sum(1 << self.cbn[a] for a in range(self.n_arrays))
+
+
+_lib = None
+
+
+def lib():
+    """The loaded libcbaa; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"libcbaa.so not built at {LIB_PATH}: run __graft_entry__.build()")
+    L = C.CDLL(LIB_PATH)
+    cfgp = C.POINTER(cbaa_config)
+    vp, u64, i32, dbl = C.c_void_p, C.c_uint64, C.c_int, C.c_double
+    sig = {
+        "cbaa_abi_version": (C.c_uint32, []),
+        "cbaa_config_default": (i32, [cfgp]),
+        "cbaa_config_validate": (i32, [cfgp]),
+        "cbaa_cube_bytes": (u64, [cfgp]),
+        "cbaa_update_scratch_bytes": (u64, [cfgp, u64, i32]),
+        "cbaa_restore_scratch_bytes": (u64, [cfgp, u64]),
+        "cbaa_cube_init": (i32, [cfgp, vp, vp]),
+        "cbaa_update": (i32, [cfgp, vp, vp, u64, i32, vp, u64, vp]),
+        "cbaa_update2": (i32, [cfgp, vp, vp, vp, u64, vp, u64, vp]),
+        "cbaa_merge_or": (i32, [cfgp, vp, C.POINTER(vp), i32, vp]),
+        "cbaa_column_zeros": (i32, [cfgp, vp, vp, vp, vp]),
+        "cbaa_restore": (i32, [cfgp, vp, dbl, i32, vp, u64, vp, u64, vp, vp]),
+        "cbaa_estimate": (i32, [cfgp, vp, vp, u64, vp, vp, vp, vp, u64, vp]),
+        "cbaa_strerror": (C.c_char_p, [i32]),
+        "cbaa_last_error": (C.c_char_p, []),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(L, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = L
+    return L
+
+
+def _check(rc: int, where: str) -> None:
+    if rc != CBAA_OK:
+        L = lib()
+        raise CbaaError(rc, where, f"{L.cbaa_strerror(rc).decode()}: {L.cbaa_last_error().decode()}")
+
+
+def _cfg(cfg) -> cbaa_config:
+    if isinstance(cfg, cbaa_config):
+        return cfg
+    if isinstance(cfg, dict):
+        cfg = Config.from_dict(cfg)
+    return cfg.to_c()
+
+
+def _stream(stream) -> Optional[int]:
+    if stream is None:
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, torch.cuda.Stream):
+        return stream.cuda_stream
+    return int(stream)
+
+
+def _dev_ptr(t: Optional[torch.Tensor], name: str) -> Optional[int]:
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError(f"{name} must be a device tensor")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t.data_ptr()
+
+
+# ---- C ABI, one to one ------------------------------------------------------
+
+def cbaa_abi_version() -> int:
+    return int(lib().cbaa_abi_version())
+
+
+def cbaa_config_default() -> Config:
+    c = cbaa_config()
+    _check(lib().cbaa_config_default(C.byref(c)), "cbaa_config_default")
+    return Config(r=c.r, n_ra=c.n_ra, n_va=c.n_va, log2_g=c.log2_g, cbn=tuple(c.cbn)[:4],
+                  cl_bs=tuple(c.cl_bs)[:3], seed_mangle=c.seed_mangle, seed_bv=c.seed_bv,
+                  seed_va=tuple(c.seed_va))
+
+
+def cbaa_config_validate(cfg) -> int:
+    return int(lib().cbaa_config_validate(C.byref(_cfg(cfg))))
+
+
+def cbaa_last_error() -> str:
+    return lib().cbaa_last_error().decode()
+
+
+def cbaa_cube_bytes(cfg) -> int:
+    return int(lib().cbaa_cube_bytes(C.byref(_cfg(cfg))))
+
+
+def cbaa_update_scratch_bytes(cfg, n_pairs: int, n_cubes: int) -> int:
+    return int(lib().cbaa_update_scratch_bytes(C.byref(_cfg(cfg)), n_pairs, n_cubes))
+
+
+def cbaa_restore_scratch_bytes(cfg, capacity: int) -> int:
+    return int(lib().cbaa_restore_scratch_bytes(C.byref(_cfg(cfg)), capacity))
+
+
+def cbaa_cube_init(cfg, cube: torch.Tensor, stream=None) -> None:
+    _check(lib().cbaa_cube_init(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"), _stream(stream)),
+           "cbaa_cube_init")
+
+
+def _pairs_ptr(pairs: torch.Tensor) -> tuple[Optional[int], int]:
+    if pairs.element_size() != 4 or pairs.dim() != 2 or pairs.shape[1] != 2:
+        raise ValueError("pairs must be a [N, 2] tensor of 32-bit integers")
+    n = int(pairs.shape[0])
+    return (_dev_ptr(pairs, "pairs") if n else None), n
+
+
+def cbaa_update(cfg, cube: torch.Tensor, pairs: torch.Tensor, side: int,
+                scratch: Optional[torch.Tensor] = None, stream=None) -> None:
+    p, n = _pairs_ptr(pairs)
+    sb = scratch.numel() * scratch.element_size() if scratch is not None else 0
+    _check(lib().cbaa_update(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"), p, n, side,
+                             _dev_ptr(scratch, "scratch"), sb, _stream(stream)), "cbaa_update")
+
+
+def cbaa_update2(cfg, cube_src: torch.Tensor, cube_dst: torch.Tensor, pairs: torch.Tensor,
+                 scratch: Optional[torch.Tensor] = None, stream=None) -> None:
+    p, n = _pairs_ptr(pairs)
+    sb = scratch.numel() * scratch.element_size() if scratch is not None else 0
+    _check(lib().cbaa_update2(C.byref(_cfg(cfg)), _dev_ptr(cube_src, "cube_src"),
+                              _dev_ptr(cube_dst, "cube_dst"), p, n, _dev_ptr(scratch, "scratch"),
+                              sb, _stream(stream)), "cbaa_update2")
+
+
+def cbaa_merge_or(cfg, dst: torch.Tensor, srcs: Sequence[torch.Tensor], stream=None) -> None:
+    arr = (C.c_void_p * len(srcs))(*[_dev_ptr(s, "src") for s in srcs])
+    _check(lib().cbaa_merge_or(C.byref(_cfg(cfg)), _dev_ptr(dst, "dst"), arr, len(srcs),
+                               _stream(stream)), "cbaa_merge_or")
+
+
+def cbaa_column_zeros(cfg, cube: torch.Tensor, zeros: torch.Tensor, ones: torch.Tensor,
+                      stream=None) -> None:
+    _check(lib().cbaa_column_zeros(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"),
+                                   _dev_ptr(zeros, "zeros"), _dev_ptr(ones, "ones"),
+                                   _stream(stream)), "cbaa_column_zeros")
+
+
+def cbaa_restore(cfg, cube: torch.Tensor, theta: float, rule: int, scratch: torch.Tensor,
+                 out: Optional[torch.Tensor], capacity: int, stats: torch.Tensor,
+                 stream=None) -> None:
+    sb = scratch.numel() * scratch.element_size()
+    _check(lib().cbaa_restore(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"), float(theta), rule,
+                              _dev_ptr(scratch, "scratch"), sb,
+                              _dev_ptr(out, "out") if capacity else None, capacity,
+                              _dev_ptr(stats, "stats"), _stream(stream)), "cbaa_restore")
+
+
+def cbaa_estimate(cfg, cube: torch.Tensor, hosts: torch.Tensor, est: torch.Tensor,
+                  zeros: torch.Tensor, layer_zeros: Optional[torch.Tensor],
+                  scratch: torch.Tensor, stream=None) -> None:
+    n = int(hosts.numel())
+    sb = scratch.numel() * scratch.element_size()
+    _check(lib().cbaa_estimate(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"),
+                               _dev_ptr(hosts, "hosts") if n else None, n,
+                               _dev_ptr(est, "est") if n else None,
+                               _dev_ptr(zeros, "zeros") if n else None,
+                               _dev_ptr(layer_zeros, "layer_zeros") if n else None,
+                               _dev_ptr(scratch, "scratch"), sb, _stream(stream)),
+           "cbaa_estimate")
+
+
+# ---- conveniences (torch allocation around the calls above) -------------------
+
+def new_cube(cfg, device="cuda", init: bool = True, stream=None) -> torch.Tensor:
+    nbytes = cbaa_cube_bytes(cfg)
+    if nbytes == 0:
+        _check(CBAA_ECONFIG, "new_cube")
+    cube = torch.empty(nbytes // 8, dtype=torch.int64, device=device)
+    if init:
+        cbaa_cube_init(cfg, cube, stream)
+    return cube
+
+
+def scratch_tensor(nbytes: int, device="cuda") -> torch.Tensor:
+    return torch.empty(max(nbytes, 256), dtype=torch.uint8, device=device)
+
+
+def stats_tensor(device="cuda") -> torch.Tensor:
+    return torch.zeros(4, dtype=torch.int64, device=device)
+
+
+def host_list(out: torch.Tensor, n: int) -> np.ndarray:
+    raw = out[: n * HOST_BYTES].cpu().numpy()
+    return raw.view(HOST_DTYPE).copy()
+
+
+def restore(cfg, cube: torch.Tensor, theta: float, rule: int = THR_THM2, capacity: int = 1 << 16,
+            stream=None) -> tuple[np.ndarray, dict]:
+    """Restores the super hosts of `cube`; grows the output until it fits.
+    Returns (structured array sorted by ip, stats dict)."""
+    dev = cube.device
+    while True:
+        scratch = scratch_tensor(cbaa_restore_scratch_bytes(cfg, capacity), dev)
+        out = torch.empty(max(capacity, 1) * HOST_BYTES, dtype=torch.uint8, device=dev)
+        st = stats_tensor(dev)
+        cbaa_restore(cfg, cube, theta, rule, scratch, out, capacity, st, stream)
+        torch.cuda.synchronize(dev)
+        s = [int(v) for v in st.cpu().tolist()]
+        stats = dict(n_hosts=s[0], hot_columns=s[1], partial_checked=s[2], tuples_checked=s[3])
+        if s[0] <= capacity:
+            return host_list(out, s[0]), stats
+        capacity = s[0]
+
+
+def estimate(cfg, cube: torch.Tensor, hosts: np.ndarray, layers: bool = False, stream=None):
+    """Thm. 2 estimates for inner IPs: (est float64, zeros uint16[, layer zeros])."""
+    dev = cube.device
+    n = int(len(hosts))
+    A = Config.from_dict(cfg).n_arrays if isinstance(cfg, dict) else cfg.n_arrays
+    h = torch.from_numpy(np.ascontiguousarray(hosts, dtype=np.uint32).view(np.int32)).to(dev)
+    est = torch.empty(max(n, 1), dtype=torch.float64, device=dev)
+    zeros = torch.empty(max(n, 1), dtype=torch.int16, device=dev)
+    lz = torch.empty(max(n, 1) * A, dtype=torch.int16, device=dev) if layers else None
+    scratch = scratch_tensor(cbaa_restore_scratch_bytes(cfg, 0), dev)
+    cbaa_estimate(cfg, cube, h, est, zeros, lz, scratch, stream)
+    torch.cuda.synchronize(dev)
+    res = (est[:n].cpu().numpy(), zeros[:n].cpu().numpy().view(np.uint16))
+    if layers:
+        res = res + (lz[: n * A].cpu().numpy().view(np.uint16).reshape(n, A),)
+    return res
+
+
+def pairs_to_device(pairs: np.ndarray, device="cuda") -> torch.Tensor:
+    """uint32 [N, 2] host pairs -> int32 [N, 2] device tensor (same bits)."""
+    a = np.ascontiguousarray(pairs, dtype=np.uint32).view(np.int32)
+    return torch.from_numpy(a).to(device)
+
+
+def cube_to_numpy(cube: torch.Tensor) -> np.ndarray:
+    return cube.cpu().numpy().view(np.uint64)

@@ -1,0 +1,266 @@
+"""Parity of the HIP path (through the C ABI) with the CPU oracle.
+
+Bar: cube bytes, per-column zeros, array fills, restored IP / Z / sketch /
+flag lists bit-exact; estimates within |d| <= 1e-9 * max(1, est) (device
+log vs libm log, everything else is exact integer or the same IEEE double
+operations in the same order)."""
+
+import numpy as np
+import pytest
+
+import oracle as O
+import tracegen
+from conftest import TINY_CONFIGS, default_params, tiny_trace
+
+pytestmark = pytest.mark.gpu
+
+EST_RTOL = 1e-9
+
+
+@pytest.fixture(scope="module")
+def cb():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_1901_06207_amd import cbaa
+    cbaa.lib()
+    return cbaa
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+def _gpu_cube(cb, p, pairs, side, scratch=None):
+    cube = cb.new_cube(p)
+    cb.cbaa_update(p, cube, cb.pairs_to_device(pairs), side, scratch)
+    return cube
+
+
+def _assert_hosts_equal(got, want):
+    assert got.size == want.size, (got.size, want.size)
+    for f in ("ip", "zeros", "cs", "flags"):
+        assert np.array_equal(got[f], want[f]), f
+    tol = EST_RTOL * np.maximum(1.0, np.abs(want["est"]))
+    assert np.all(np.abs(got["est"] - want["est"]) <= tol)
+
+
+# ---------------------------------------------------------------- update
+
+@pytest.mark.parametrize("name", sorted(TINY_CONFIGS))
+@pytest.mark.parametrize("side", [0, 1])
+def test_update_tiny_configs_bitexact(cb, name, side):
+    p = TINY_CONFIGS[name]
+    t = tiny_trace(100 + side, n_hosts=3000, n_planted=30, fan_in=0.3)
+    _say(name, side, t.n)
+    got = cb.cube_to_numpy(_gpu_cube(cb, p, t.pairs, side))
+    assert np.array_equal(got, O.cube_of(p, t.pairs, side))
+
+
+def test_update_small_window_bitexact(cb, small_window):
+    p = default_params()
+    _say("small window", small_window.n)
+    got = cb.cube_to_numpy(_gpu_cube(cb, p, small_window.pairs, 0))
+    assert np.array_equal(got, O.cube_of(p, small_window.pairs, 0))
+
+
+def test_update2_both_sides_bitexact(cb):
+    import torch
+    p = default_params()
+    t = tracegen.window_core_edge(12, scale=1 / 16)
+    _say("update2", t.n)
+    a, b = cb.new_cube(p), cb.new_cube(p)
+    cb.cbaa_update2(p, a, b, cb.pairs_to_device(t.pairs))
+    torch.cuda.synchronize()
+    assert np.array_equal(cb.cube_to_numpy(a), O.cube_of(p, t.pairs, 0))
+    assert np.array_equal(cb.cube_to_numpy(b), O.cube_of(p, t.pairs, 1))
+
+
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1000003])
+def test_update_ragged_sizes(cb, n):
+    p = default_params()
+    rng = np.random.default_rng(n)
+    pairs = rng.integers(0, 1 << 32, (n, 2), dtype=np.uint64).astype(np.uint32)
+    _say("ragged", n)
+    got = cb.cube_to_numpy(_gpu_cube(cb, p, pairs, 0))
+    assert np.array_equal(got, O.cube_of(p, pairs, 0))
+
+
+def test_update_skewed_single_host_and_repeats(cb):
+    p = default_params()
+    rng = np.random.default_rng(5)
+    n = 2_000_000
+    one_host = np.stack([np.full(n, 0x0A0B0C0D, np.uint32),
+                         rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)], axis=1)
+    same_pair = np.tile(np.array([[1, 2]], np.uint32), (n, 1))
+    for pairs in (one_host, same_pair):
+        got = cb.cube_to_numpy(_gpu_cube(cb, p, pairs, 0))
+        assert np.array_equal(got, O.cube_of(p, pairs, 0))
+
+
+def test_update_concurrent_streams_and_batches(cb):
+    """The same cube updated from several streams in random-size batches is
+    the cube of the whole window."""
+    import torch
+    p = default_params()
+    t = tracegen.window_core_edge(13, scale=1 / 32)
+    rng = np.random.default_rng(6)
+    cuts = np.sort(rng.choice(np.arange(1, t.n), 9, replace=False))
+    parts = np.split(t.pairs, cuts)
+    cube = cb.new_cube(p)
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in range(3)]
+    dev = [cb.pairs_to_device(q) for q in parts]
+    torch.cuda.synchronize()
+    for i, q in enumerate(dev):
+        cb.cbaa_update(p, cube, q, 0, stream=streams[i % 3])
+    torch.cuda.synchronize()
+    assert np.array_equal(cb.cube_to_numpy(cube), O.cube_of(p, t.pairs, 0))
+
+
+# ---------------------------------------------------------------- merge
+
+def test_merge_or_router_split(cb):
+    import torch
+    p = default_params()
+    t = tracegen.window_core_edge(14, scale=1 / 64)
+    parts = tracegen.split_routers(t.pairs, 11, seed=3)
+    cubes = [_gpu_cube(cb, p, q, 0) for q in parts]
+    whole = O.cube_of(p, t.pairs, 0)
+    dst = cb.new_cube(p, init=False)
+    cb.cbaa_merge_or(p, dst, cubes)          # 11 sources: two launches
+    torch.cuda.synchronize()
+    assert np.array_equal(cb.cube_to_numpy(dst), whole)
+    cb.cbaa_merge_or(p, cubes[5], cubes[:7])  # destination aliases a source
+    torch.cuda.synchronize()
+    assert np.array_equal(cb.cube_to_numpy(cubes[5]),
+                          O.cube_of(p, np.concatenate(parts[:7]), 0))
+
+
+# ---------------------------------------------------------------- column statistics
+
+@pytest.mark.parametrize("name", ["default_g64", "hetero_r5", "g128_r3"])
+def test_column_zeros_and_fills(cb, name):
+    import torch
+    p = TINY_CONFIGS[name]
+    t = tiny_trace(7, n_hosts=5000, n_planted=40)
+    cube = _gpu_cube(cb, p, t.pairs, 0)
+    S = 1 << p["r"]
+    A = p["n_ra"] + p["n_va"]
+    W = sum(1 << p["cbn"][a] for a in range(A))
+    zeros = torch.empty(S * W, dtype=torch.int16, device="cuda")
+    ones = torch.empty(S * A, dtype=torch.int32, device="cuda")
+    cb.cbaa_column_zeros(p, cube, zeros, ones)
+    torch.cuda.synchronize()
+    wz, wo = O.column_zeros(p, O.cube_of(p, t.pairs, 0))
+    assert np.array_equal(zeros.cpu().numpy().view(np.uint16), wz)
+    assert np.array_equal(ones.cpu().numpy().view(np.uint32), wo)
+
+
+# ---------------------------------------------------------------- restore
+
+@pytest.mark.parametrize("name", sorted(TINY_CONFIGS))
+@pytest.mark.parametrize("rule", [0, 1])
+def test_restore_tiny_configs(cb, name, rule):
+    p = TINY_CONFIGS[name]
+    theta = 16.0 if p["log2_g"] == 6 else 32.0
+    t = tiny_trace(200 + rule, n_hosts=3000, n_planted=30, fan_in=0.3)
+    cube_np = O.cube_of(p, t.pairs, 0)
+    _say("restore", name, rule)
+    cube = _gpu_cube(cb, p, t.pairs, 0)
+    got, st = cb.restore(p, cube, theta, rule)
+    want, wst = O.restore(p, cube_np, theta, rule)
+    assert st["hot_columns"] == wst["hot_columns"]
+    assert st["tuples_checked"] <= wst["cp_valid"]
+    _assert_hosts_equal(got, want)
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3])
+def test_restore_small_window(cb, seed):
+    p = default_params()
+    t = tracegen.window_small(seed)
+    cube = _gpu_cube(cb, p, t.pairs, 0)
+    got, st = cb.restore(p, cube, 1024.0)
+    want, wst = O.restore(p, O.cube_of(p, t.pairs, 0), 1024.0)
+    _say("small window restore", seed, got.size, st)
+    assert got.size > 50
+    _assert_hosts_equal(got, want)
+
+
+def test_restore_capacity_overflow_and_empty(cb):
+    import torch
+    p = default_params()
+    t = tracegen.window_small(4)
+    cube = _gpu_cube(cb, p, t.pairs, 0)
+    scratch = cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, 8))
+    out = torch.empty(8 * 16, dtype=torch.uint8, device="cuda")
+    st = cb.stats_tensor()
+    cb.cbaa_restore(p, cube, 1024.0, 0, scratch, out, 8, st)
+    torch.cuda.synchronize()
+    assert int(st[0]) > 8
+    full, _ = cb.restore(p, cube, 1024.0, capacity=8)   # grows and retries
+    assert full.size == int(st[0])
+    empty, est = cb.restore(p, cb.new_cube(p), 1024.0)
+    assert empty.size == 0 and est["hot_columns"] == 0
+    # capacity 0: counts only
+    scratch0 = cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, 0))
+    cb.cbaa_restore(p, cube, 1024.0, 0, scratch0, None, 0, st)
+    torch.cuda.synchronize()
+    assert int(st[0]) == full.size
+
+
+def test_restore_saturated_host(cb):
+    import torch
+    p = TINY_CONFIGS["ra4_va2"]
+    host = 0xC0A80001
+    pairs = np.stack([np.full(20000, host, np.uint32),
+                      np.arange(20000, dtype=np.uint32) * np.uint32(2654435761)], axis=1)
+    cube = _gpu_cube(cb, p, pairs, 0)
+    got, _ = cb.restore(p, cube, 16.0)
+    want, _ = O.restore(p, O.cube_of(p, pairs, 0), 16.0)
+    _assert_hosts_equal(got, want)
+    assert host in got["ip"].tolist()
+    assert got["flags"][got["ip"] == host][0] == cb.FLAG_SATURATED
+
+
+# ---------------------------------------------------------------- estimate
+
+def test_estimate_matches_oracle(cb):
+    p = default_params()
+    t = tracegen.window_small(5)
+    cube = _gpu_cube(cb, p, t.pairs, 0)
+    rng = np.random.default_rng(2)
+    hosts = np.concatenate([t.planted_ips, t.bg_ips[:5000],
+                            rng.integers(0, 1 << 32, 1000, dtype=np.uint64).astype(np.uint32)])
+    est, zeros, layers = cb.estimate(p, cube, hosts, layers=True)
+    cube_np = O.cube_of(p, t.pairs, 0)
+    west, wz, _ = O.estimate(p, cube_np, hosts)
+    assert np.array_equal(zeros, wz)
+    assert np.all(np.abs(est - west) <= EST_RTOL * np.maximum(1.0, west))
+    assert np.array_equal(layers, O.host_layer_zeros(p, cube_np, hosts))
+
+
+# ---------------------------------------------------------------- full core-edge window
+
+@pytest.fixture(scope="module")
+def core_edge():
+    return tracegen.window_core_edge(11)
+
+
+def test_full_core_edge_window(cb, core_edge):
+    """The 64Mi-packet window in the benchmark's configuration: both cubes
+    bit-exact and both restored lists equal to the oracle's."""
+    import torch
+    p = default_params()
+    t = core_edge
+    _say("core-edge full", t.n)
+    a, b = cb.new_cube(p), cb.new_cube(p)
+    cb.cbaa_update2(p, a, b, cb.pairs_to_device(t.pairs))
+    torch.cuda.synchronize()
+    for side, cube in ((0, a), (1, b)):
+        want_cube = O.cube_of(p, t.pairs, side)
+        assert np.array_equal(cb.cube_to_numpy(cube), want_cube)
+        got, st = cb.restore(p, cube, 1024.0)
+        want, _ = O.restore(p, want_cube, 1024.0)
+        _say("core-edge restore side", side, got.size, st)
+        _assert_hosts_equal(got, want)
