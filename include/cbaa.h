@@ -35,6 +35,7 @@ extern "C" {
 #define CBAA_MAX_RA 4
 #define CBAA_MAX_VA 2
 #define CBAA_MAX_ARRAYS (CBAA_MAX_RA + CBAA_MAX_VA)
+#define CBAA_MAX_BATCH 32
 
 /* Return codes. */
 #define CBAA_OK 0
@@ -155,7 +156,9 @@ int cbaa_cube_init(const cbaa_config* h_cfg, void* d_cube, void* stream);
  * d_scratch/scratch_bytes: NULL/0 selects direct global atomics; otherwise
  * the batch is partitioned by (sketch, row block) and applied through LDS
  * tiles, in as many passes as the scratch requires (CBAA_ESCRATCH if it holds
- * less than one pass of the minimum size). n_pairs = 0 is a no-op. */
+ * less than one pass of the minimum size). A scratch buffer belongs to one
+ * call at a time: calls that may overlap (other streams) need their own.
+ * n_pairs = 0 is a no-op. */
 int cbaa_update(const cbaa_config* h_cfg, void* d_cube, const uint32_t* d_pairs,
                 uint64_t n_pairs, int side, void* d_scratch, uint64_t scratch_bytes,
                 void* stream);
@@ -165,6 +168,45 @@ int cbaa_update(const cbaa_config* h_cfg, void* d_cube, const uint32_t* d_pairs,
 int cbaa_update2(const cbaa_config* h_cfg, void* d_cube_src, void* d_cube_dst,
                  const uint32_t* d_pairs, uint64_t n_pairs, void* d_scratch,
                  uint64_t scratch_bytes, void* stream);
+
+/* One edge router's batch inside cbaa_update_batch. */
+typedef struct cbaa_stream_batch {
+  const uint32_t* d_pairs;  /* n_pairs (source, destination) pairs, 8-byte aligned */
+  uint64_t n_pairs;
+  void* d_cube;             /* keyed by `side`; keyed by source when d_cube_dst is set */
+  void* d_cube_dst;         /* NULL, or the destination-keyed cube (both sides per read) */
+  int side;                 /* CBAA_SIDE_*; ignored when d_cube_dst is set */
+  int reserved;
+} cbaa_stream_batch;
+
+/* Tile and partition shapes of the partitioned update (0 = library default):
+ * chunk_pairs  pairs per histogram/scatter block (multiple of 1024, <= 2^22)
+ * seg_records  records per apply work item (>= 1024)
+ * apply_blocks persistent blocks of the apply step (1..65536) */
+typedef struct cbaa_tuning {
+  uint32_t chunk_pairs;
+  uint32_t seg_records;
+  uint32_t apply_blocks;
+  uint32_t reserved;
+} cbaa_tuning;
+
+/* Scratch bytes cbaa_update_batch needs for these streams and shapes. */
+uint64_t cbaa_update_batch_scratch_bytes(const cbaa_config* h_cfg,
+                                         const cbaa_stream_batch* h_streams, int k,
+                                         const cbaa_tuning* h_tuning);
+
+/* Alg. 1 for the batches of k (1..CBAA_MAX_BATCH) edge routers at once, with
+ * uneven sizes, through one sequence of launches of the partitioned path:
+ * the same result as k cbaa_update (or cbaa_update2) calls. Either every
+ * stream sets d_cube_dst or none does. Streams may share cubes. The scratch
+ * must hold the whole batch (CBAA_ESCRATCH otherwise); each stream's records
+ * (pairs x cubes) must stay below 2^32. Only enqueues device work, so the
+ * call can be captured into a HIP graph and replayed. Configurations outside
+ * the partitioned path's limits (cbaa_update_scratch_bytes returns 0) get
+ * CBAA_ECONFIG. */
+int cbaa_update_batch(const cbaa_config* h_cfg, const cbaa_stream_batch* h_streams, int k,
+                      const cbaa_tuning* h_tuning, void* d_scratch, uint64_t scratch_bytes,
+                      void* stream);
 
 /* ---- global server --------------------------------------------------- */
 

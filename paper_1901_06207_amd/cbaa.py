@@ -48,6 +48,18 @@ class cbaa_restore_stats(C.Structure):
                 ("partial_checked", C.c_uint64), ("tuples_checked", C.c_uint64)]
 
 
+class cbaa_stream_batch(C.Structure):
+    _fields_ = [("d_pairs", C.c_void_p), ("n_pairs", C.c_uint64), ("d_cube", C.c_void_p),
+                ("d_cube_dst", C.c_void_p), ("side", C.c_int), ("reserved", C.c_int)]
+
+
+class cbaa_tuning(C.Structure):
+    _fields_ = [("chunk_pairs", C.c_uint32), ("seg_records", C.c_uint32),
+                ("apply_blocks", C.c_uint32), ("reserved", C.c_uint32)]
+
+
+MAX_BATCH = 32
+
 HOST_DTYPE = np.dtype([("ip", "<u4"), ("zeros", "<u2"), ("cs", "u1"), ("flags", "u1"),
                        ("est", "<f8")])
 HOST_BYTES = 16
@@ -126,9 +138,20 @@ def lib():
         "cbaa_update": (i32, [cfgp, vp, vp, u64, i32, vp, u64, vp]),
         "cbaa_update2": (i32, [cfgp, vp, vp, vp, u64, vp, u64, vp]),
         "cbaa_merge_or": (i32, [cfgp, vp, C.POINTER(vp), i32, vp]),
+        "cbaa_update_batch_scratch_bytes": (u64, [cfgp, C.POINTER(cbaa_stream_batch), i32,
+                                                  C.POINTER(cbaa_tuning)]),
+        "cbaa_update_batch": (i32, [cfgp, C.POINTER(cbaa_stream_batch), i32,
+                                    C.POINTER(cbaa_tuning), vp, u64, vp]),
         "cbaa_column_zeros": (i32, [cfgp, vp, vp, vp, vp]),
         "cbaa_restore": (i32, [cfgp, vp, dbl, i32, vp, u64, vp, u64, vp, vp]),
         "cbaa_estimate": (i32, [cfgp, vp, vp, u64, vp, vp, vp, vp, u64, vp]),
+        "cbaa_mlp_param_count": (C.c_uint32, [C.c_uint32]),
+        "cbaa_mlp_init": (i32, [C.c_uint32, C.c_uint32, vp, vp, vp]),
+        "cbaa_mlp_features": (i32, [cfgp, vp, vp, u64, C.c_uint32, vp, vp, u64, vp]),
+        "cbaa_mlp_forward": (i32, [C.c_uint32, vp, vp, vp, u64, vp, vp]),
+        "cbaa_mlp_loss_grad": (i32, [C.c_uint32, vp, vp, vp, vp, u64, vp, vp, vp]),
+        "cbaa_mlp_adam": (i32, [C.c_uint32, vp, vp, vp, vp, vp, C.c_uint32, C.c_float,
+                                C.c_float, C.c_float, C.c_float, vp]),
         "cbaa_strerror": (C.c_char_p, [i32]),
         "cbaa_last_error": (C.c_char_p, []),
     }
@@ -235,6 +258,42 @@ def cbaa_update2(cfg, cube_src: torch.Tensor, cube_dst: torch.Tensor, pairs: tor
                               sb, _stream(stream)), "cbaa_update2")
 
 
+def _stream_table(streams):
+    """streams: sequence of (pairs, cube, cube_dst or None, side)."""
+    arr = (cbaa_stream_batch * len(streams))()
+    for i, (pairs, cube, cube_dst, side) in enumerate(streams):
+        p, n = _pairs_ptr(pairs)
+        arr[i].d_pairs = p
+        arr[i].n_pairs = n
+        arr[i].d_cube = _dev_ptr(cube, "cube")
+        arr[i].d_cube_dst = _dev_ptr(cube_dst, "cube_dst")
+        arr[i].side = side
+    return arr
+
+
+def _tuning(t) -> Optional[cbaa_tuning]:
+    if t is None:
+        return None
+    if isinstance(t, cbaa_tuning):
+        return t
+    return cbaa_tuning(int(t.get("chunk_pairs", 0)), int(t.get("seg_records", 0)),
+                       int(t.get("apply_blocks", 0)), 0)
+
+
+def cbaa_update_batch_scratch_bytes(cfg, streams, tuning=None) -> int:
+    t = _tuning(tuning)
+    return int(lib().cbaa_update_batch_scratch_bytes(C.byref(_cfg(cfg)), _stream_table(streams),
+                                                     len(streams), C.byref(t) if t else None))
+
+
+def cbaa_update_batch(cfg, streams, scratch: torch.Tensor, tuning=None, stream=None) -> None:
+    t = _tuning(tuning)
+    sb = scratch.numel() * scratch.element_size()
+    _check(lib().cbaa_update_batch(C.byref(_cfg(cfg)), _stream_table(streams), len(streams),
+                                   C.byref(t) if t else None, _dev_ptr(scratch, "scratch"), sb,
+                                   _stream(stream)), "cbaa_update_batch")
+
+
 def cbaa_merge_or(cfg, dst: torch.Tensor, srcs: Sequence[torch.Tensor], stream=None) -> None:
     arr = (C.c_void_p * len(srcs))(*[_dev_ptr(s, "src") for s in srcs])
     _check(lib().cbaa_merge_or(C.byref(_cfg(cfg)), _dev_ptr(dst, "dst"), arr, len(srcs),
@@ -270,6 +329,54 @@ def cbaa_estimate(cfg, cube: torch.Tensor, hosts: torch.Tensor, est: torch.Tenso
                                _dev_ptr(layer_zeros, "layer_zeros") if n else None,
                                _dev_ptr(scratch, "scratch"), sb, _stream(stream)),
            "cbaa_estimate")
+
+
+# ---- learned estimator (include/cbaa_mlp.h) ------------------------------------
+
+def cbaa_mlp_param_count(n_features: int) -> int:
+    return int(lib().cbaa_mlp_param_count(n_features))
+
+
+def cbaa_mlp_init(n_features: int, seed: int, master: torch.Tensor, wbf: torch.Tensor,
+                  stream=None) -> None:
+    _check(lib().cbaa_mlp_init(n_features, seed, _dev_ptr(master, "master"), _dev_ptr(wbf, "wbf"),
+                               _stream(stream)), "cbaa_mlp_init")
+
+
+def cbaa_mlp_features(cfg, cube: torch.Tensor, hosts: torch.Tensor, n_features: int,
+                      x: torch.Tensor, scratch: torch.Tensor, stream=None) -> None:
+    n = int(hosts.numel())
+    sb = scratch.numel() * scratch.element_size()
+    _check(lib().cbaa_mlp_features(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"),
+                                   _dev_ptr(hosts, "hosts") if n else None, n, n_features,
+                                   _dev_ptr(x, "x") if n else None, _dev_ptr(scratch, "scratch"),
+                                   sb, _stream(stream)), "cbaa_mlp_features")
+
+
+def cbaa_mlp_forward(n_features: int, master: torch.Tensor, wbf: torch.Tensor, x: torch.Tensor,
+                     y: torch.Tensor, stream=None) -> None:
+    n = int(y.numel())
+    _check(lib().cbaa_mlp_forward(n_features, _dev_ptr(master, "master"), _dev_ptr(wbf, "wbf"),
+                                  _dev_ptr(x, "x") if n else None, n,
+                                  _dev_ptr(y, "y") if n else None, _stream(stream)),
+           "cbaa_mlp_forward")
+
+
+def cbaa_mlp_loss_grad(n_features: int, master: torch.Tensor, wbf: torch.Tensor, x: torch.Tensor,
+                       t: torch.Tensor, grad: torch.Tensor, loss: torch.Tensor,
+                       stream=None) -> None:
+    _check(lib().cbaa_mlp_loss_grad(n_features, _dev_ptr(master, "master"), _dev_ptr(wbf, "wbf"),
+                                    _dev_ptr(x, "x"), _dev_ptr(t, "t"), int(t.numel()),
+                                    _dev_ptr(grad, "grad"), _dev_ptr(loss, "loss"),
+                                    _stream(stream)), "cbaa_mlp_loss_grad")
+
+
+def cbaa_mlp_adam(n_features: int, master: torch.Tensor, wbf: torch.Tensor, grad: torch.Tensor,
+                  m: torch.Tensor, v: torch.Tensor, step: int, lr: float, beta1: float = 0.9,
+                  beta2: float = 0.999, eps: float = 1e-8, stream=None) -> None:
+    _check(lib().cbaa_mlp_adam(n_features, _dev_ptr(master, "master"), _dev_ptr(wbf, "wbf"),
+                               _dev_ptr(grad, "grad"), _dev_ptr(m, "m"), _dev_ptr(v, "v"), step,
+                               lr, beta1, beta2, eps, _stream(stream)), "cbaa_mlp_adam")
 
 
 # ---- conveniences (torch allocation around the calls above) -------------------

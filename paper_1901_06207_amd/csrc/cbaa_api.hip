@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include "../../include/cbaa_mlp.h"
 #include "cbaa_internal.hpp"
 
 namespace cbaa {
@@ -163,10 +164,10 @@ static int update_common(const Dims& d, void* c0, void* c1, const uint32_t* pair
   hipStream_t s = (hipStream_t)stream;
   if (scratch == nullptr || scratch_bytes == 0 || !partitioned_supported(d))
     return launch_update_direct(d, (uint64_t*)c0, (uint64_t*)c1, pairs, n, side, s);
-  if (scratch_bytes < partitioned_min_scratch_bytes(d, c1 ? 2 : 1)) {
+  if (scratch_bytes < partitioned_min_scratch_bytes(d, c1 ? 2 : 1, n)) {
     set_error("update scratch of %llu bytes is below the minimum %llu",
               (unsigned long long)scratch_bytes,
-              (unsigned long long)partitioned_min_scratch_bytes(d, c1 ? 2 : 1));
+              (unsigned long long)partitioned_min_scratch_bytes(d, c1 ? 2 : 1, n));
     return CBAA_ESCRATCH;
   }
   REQUIRE(((uintptr_t)scratch & 255u) == 0, "scratch must be 256-byte aligned");
@@ -188,6 +189,62 @@ int cbaa_update2(const cbaa_config* cfg, void* d_cube_src, void* d_cube_dst,
   REQUIRE(d_cube_src != d_cube_dst, "the two cubes must differ");
   return update_common(d, d_cube_src, d_cube_dst, d_pairs, n_pairs, CBAA_SIDE_SRC, d_scratch,
                        scratch_bytes, stream);
+}
+
+// Checks a stream table; returns the cube count (1 or 2) or a negative code.
+static int check_streams(const Dims& d, const cbaa_stream_batch* h, int k, StreamSpec* out) {
+  REQUIRE(h && k >= 1 && k <= CBAA_MAX_BATCH, "need 1..%d streams", CBAA_MAX_BATCH);
+  if (!partitioned_supported(d)) {
+    set_error("configuration outside the partitioned update's limits");
+    return CBAA_ECONFIG;
+  }
+  const int nc = h[0].d_cube_dst ? 2 : 1;
+  for (int i = 0; i < k; ++i) {
+    const cbaa_stream_batch& s = h[i];
+    REQUIRE((s.d_cube_dst != nullptr) == (nc == 2), "streams mix one- and two-cube updates");
+    REQUIRE(s.d_cube && ((uintptr_t)s.d_cube & 15u) == 0, "stream %d: cube null or misaligned", i);
+    REQUIRE(!s.d_cube_dst || ((uintptr_t)s.d_cube_dst & 15u) == 0,
+            "stream %d: destination cube misaligned", i);
+    REQUIRE(s.d_cube != s.d_cube_dst, "stream %d: the two cubes must differ", i);
+    REQUIRE(nc == 2 || s.side == CBAA_SIDE_SRC || s.side == CBAA_SIDE_DST, "stream %d: bad side", i);
+    REQUIRE(s.n_pairs == 0 || (s.d_pairs && ((uintptr_t)s.d_pairs & 7u) == 0),
+            "stream %d: pairs null or misaligned", i);
+    REQUIRE((uint64_t)nc * s.n_pairs < 0xFFFFFFFFull, "stream %d: too many records", i);
+    out[i].pairs = s.d_pairs;
+    out[i].n = s.n_pairs;
+    out[i].cube0 = (uint64_t*)s.d_cube;
+    out[i].cube1 = (uint64_t*)s.d_cube_dst;
+    out[i].side = nc == 2 ? CBAA_SIDE_SRC : s.side;
+  }
+  return nc;
+}
+
+uint64_t cbaa_update_batch_scratch_bytes(const cbaa_config* cfg, const cbaa_stream_batch* h,
+                                         int k, const cbaa_tuning* t) {
+  Dims d;
+  if (!make_dims(cfg, &d) || !tuning_valid(t)) return 0;
+  StreamSpec sp[CBAA_MAX_BATCH];
+  const int nc = check_streams(d, h, k, sp);
+  if (nc < 0) return 0;
+  return batch_scratch_bytes(d, sp, k, nc, t);
+}
+
+int cbaa_update_batch(const cbaa_config* cfg, const cbaa_stream_batch* h, int k,
+                      const cbaa_tuning* t, void* d_scratch, uint64_t scratch_bytes,
+                      void* stream) {
+  CHECK_DIMS(cfg, d);
+  REQUIRE(tuning_valid(t), "tuning out of range");
+  StreamSpec sp[CBAA_MAX_BATCH];
+  const int nc = check_streams(d, h, k, sp);
+  if (nc < 0) return nc;
+  const uint64_t need = batch_scratch_bytes(d, sp, k, nc, t);
+  if (!d_scratch || scratch_bytes < need) {
+    set_error("batch scratch of %llu bytes is below the required %llu",
+              (unsigned long long)scratch_bytes, (unsigned long long)need);
+    return CBAA_ESCRATCH;
+  }
+  REQUIRE(((uintptr_t)d_scratch & 255u) == 0, "scratch must be 256-byte aligned");
+  return launch_update_batch(d, sp, k, nc, t, d_scratch, (hipStream_t)stream);
 }
 
 int cbaa_merge_or(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
@@ -249,6 +306,25 @@ int cbaa_estimate(const cbaa_config* cfg, const void* d_cube, const uint32_t* d_
   REQUIRE(n < (1ull << 32), "n must be below 2^32");
   return launch_estimate(d, (const uint64_t*)d_cube, d_hosts, n, d_est, d_zeros, d_layer_zeros,
                          d_scratch, (hipStream_t)stream);
+}
+
+int cbaa_mlp_features(const cbaa_config* cfg, const void* d_cube, const uint32_t* d_hosts,
+                      uint64_t n, uint32_t n_features, float* d_x, void* d_scratch,
+                      uint64_t scratch_bytes, void* stream) {
+  CHECK_DIMS(cfg, d);
+  REQUIRE(d_cube && ((uintptr_t)d_cube & 15u) == 0, "cube must be 16-byte aligned");
+  REQUIRE(n_features == d.A || n_features == d.A + 2, "n_features must be A or A + 2");
+  REQUIRE(n_features <= 8, "at most 8 features");
+  REQUIRE(d_scratch && ((uintptr_t)d_scratch & 255u) == 0, "scratch must be 256-byte aligned");
+  if (scratch_bytes < restore_scratch_bytes(d, 0)) {
+    set_error("features scratch too small");
+    return CBAA_ESCRATCH;
+  }
+  if (n == 0) return CBAA_OK;
+  REQUIRE(d_hosts && d_x, "null host list or output");
+  REQUIRE(n < (1ull << 32), "n must be below 2^32");
+  return launch_features(d, (const uint64_t*)d_cube, d_hosts, n, n_features, d_x, d_scratch,
+                         (hipStream_t)stream);
 }
 
 const char* cbaa_strerror(int code) {

@@ -101,6 +101,15 @@ __device__ inline uint32_t va_col(const Dims& d, int j, uint32_t lp) {
   return lowbias32(lp ^ d.seed_va[j]) >> (32u - d.cbn[d.n_ra + j]);
 }
 
+// One stream of a partitioned batch (host side).
+struct StreamSpec {
+  const uint32_t* pairs;
+  uint64_t n;
+  uint64_t* cube0;
+  uint64_t* cube1;
+  int side;
+};
+
 // ---- host-side helpers (cbaa_api.hip) ----------------------------------
 
 bool make_dims(const cbaa_config* cfg, Dims* out);
@@ -115,8 +124,13 @@ int launch_update_partitioned(const Dims& d, uint64_t* cube0, uint64_t* cube1,
                               const uint32_t* pairs, uint64_t n, int side, void* scratch,
                               uint64_t scratch_bytes, hipStream_t s);
 uint64_t partitioned_scratch_bytes(const Dims& d, uint64_t n_pairs, int n_cubes);
-uint64_t partitioned_min_scratch_bytes(const Dims& d, int n_cubes);
+uint64_t partitioned_min_scratch_bytes(const Dims& d, int n_cubes, uint64_t n_pairs);
 bool partitioned_supported(const Dims& d);
+bool tuning_valid(const cbaa_tuning* t);
+uint64_t batch_scratch_bytes(const Dims& d, const StreamSpec* specs, int k, int n_cubes,
+                             const cbaa_tuning* t);
+int launch_update_batch(const Dims& d, const StreamSpec* specs, int k, int n_cubes,
+                        const cbaa_tuning* t, void* scratch, hipStream_t s);
 int launch_merge_or(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
                     hipStream_t s);
 int launch_column_zeros(const Dims& d, const uint64_t* cube, uint16_t* zeros, uint32_t* ones,
@@ -124,6 +138,8 @@ int launch_column_zeros(const Dims& d, const uint64_t* cube, uint16_t* zeros, ui
 uint64_t restore_scratch_bytes(const Dims& d, uint64_t capacity);
 int launch_restore(const Dims& d, const uint64_t* cube, double x_theta, int rule, void* scratch,
                    uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s);
+int launch_features(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
+                    uint32_t F, float* x, void* scratch, hipStream_t s);
 int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
                     double* est, uint16_t* zeros, uint16_t* layer_zeros, void* scratch,
                     hipStream_t s);

@@ -1,15 +1,584 @@
-// Partitioned update path (LDS tiles). Not enabled yet: callers fall back to
-// direct atomics.
+// Partitioned update. The bit-sets of a batch are binned by (cube, sketch,
+// 64-bit row block) so that each bin's target -- one row block of every column
+// of one sketch, W contiguous words (128 KiB at the paper's dimensions) -- can
+// be assembled in LDS and OR-ed into the cube once, with coalesced 64-bit
+// atomic ORs. This replaces A random device-scope atomics per pair and cube
+// by a streamed 8-byte record per pair and cube.
+//
+// The same seven launches serve one edge router's batch or K routers' batches
+// of uneven sizes at once (a stream table passed by value to every kernel):
+//   1. histogram   per chunk of pairs (chunks of all streams in one grid),
+//                  records per bin in LDS counters
+//   2. group sums  chunks are grouped (never across streams); per (group, bin)
+//   3. bases       per stream: bin totals, exclusive prefixes over bins of
+//                  records and of apply segments
+//   4. items       apply items prefixed over streams
+//   5. offsets     first record of every (chunk, bin) inside its stream's
+//                  record region (bins major, so a bin's records are contiguous)
+//   6. scatter     re-read each chunk, rank its records inside their bins in
+//                  LDS, stage them bin-sorted, write every bin's run
+//                  contiguously at the bin's cursor
+//   7. apply       persistent blocks walk (stream, bin, segment) items: zero
+//                  an LDS tile, OR the records' bits into it, flush non-zero
+//                  words to the stream's cube
+// A record is the mangled inner IP and the outer IP's bit with the cube index
+// in bit 31 (uint2); the apply step recomputes the columns from the mangled IP.
 #include "cbaa_internal.hpp"
 
 namespace cbaa {
 
-bool partitioned_supported(const Dims&) { return false; }
-uint64_t partitioned_scratch_bytes(const Dims&, uint64_t, int) { return 0; }
-uint64_t partitioned_min_scratch_bytes(const Dims&, int) { return 0; }
+namespace {
+
+constexpr int kBlock = 1024;
+constexpr uint32_t kChunksPerGroup = 16;  // chunks summed per thread in the scan
+constexpr uint32_t kMaxBins = 2048;
+constexpr uint32_t kStage = 16384;        // records staged in LDS per scatter step
+constexpr int kUnroll = 8;                // independent loads in flight per thread
+constexpr int kApplyUnroll = 16;
+constexpr uint32_t kMaxTileWords = 16384; // 128 KiB LDS tile
+constexpr uint32_t kDefaultChunk = 65536;
+constexpr uint32_t kDefaultSeg = 65536;
+constexpr uint32_t kDefaultApplyBlocks = 512;
+
+inline uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
+
+struct StreamDesc {
+  const uint2* pairs;
+  uint64_t n;
+  uint64_t* cube0;
+  uint64_t* cube1;
+  uint64_t rec_base;      // first record of this stream
+  uint32_t chunk_begin;   // first global chunk
+  uint32_t group_begin;   // first global group
+  uint32_t side;
+  uint32_t pad;
+};
+
+struct Batch {
+  uint32_t k;
+  uint32_t nbins;         // per stream: n_cubes * S * R
+  uint32_t total_chunks;
+  uint32_t total_groups;
+  uint32_t chunk;         // pairs per chunk
+  uint32_t seg;           // records per apply item
+  StreamDesc s[CBAA_MAX_BATCH];
+};
+
+struct Layout {
+  uint32_t* counts;   // [total_chunks][nbins] -> offsets
+  uint32_t* gsum;     // [total_groups][nbins]
+  uint32_t* base;     // [k][nbins + 1] record offsets inside the stream
+  uint32_t* segpre;   // [k][nbins + 1] apply items inside the stream
+  uint32_t* items;    // [k + 1] apply items before each stream
+  uint2* rec;         // [sum of n_cubes * n]
+  uint64_t bytes;
+};
+
+struct Tuning {
+  uint32_t chunk, seg, apply_blocks;
+};
+
+Tuning effective(const cbaa_tuning* t) {
+  Tuning r;
+  r.chunk = (t && t->chunk_pairs) ? t->chunk_pairs : kDefaultChunk;
+  r.seg = (t && t->seg_records) ? t->seg_records : kDefaultSeg;
+  r.apply_blocks = (t && t->apply_blocks) ? t->apply_blocks : kDefaultApplyBlocks;
+  return r;
+}
+
+// Fills the batch's chunk/group/record bookkeeping and carves the scratch.
+Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
+  b.nbins = (uint32_t)n_cubes * d.S * d.R;
+  b.chunk = chunk;
+  uint32_t ch = 0, gr = 0;
+  uint64_t rec = 0;
+  for (uint32_t i = 0; i < b.k; ++i) {
+    StreamDesc& s = b.s[i];
+    const uint32_t nc = (uint32_t)((s.n + chunk - 1) / chunk);
+    s.chunk_begin = ch;
+    s.group_begin = gr;
+    s.rec_base = rec;
+    ch += nc;
+    gr += (nc + kChunksPerGroup - 1) / kChunksPerGroup;
+    rec += (uint64_t)n_cubes * s.n;
+  }
+  b.total_chunks = ch;
+  b.total_groups = gr;
+  Layout L;
+  uint64_t off = 0;
+  char* p = (char*)base;
+  auto take = [&](uint64_t bytes) {
+    char* q = p ? p + off : nullptr;
+    off += align256(bytes);
+    return (void*)q;
+  };
+  L.counts = (uint32_t*)take((uint64_t)(ch ? ch : 1) * b.nbins * 4);
+  L.gsum = (uint32_t*)take((uint64_t)(gr ? gr : 1) * b.nbins * 4);
+  L.base = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
+  L.segpre = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
+  L.items = (uint32_t*)take((uint64_t)(b.k + 1) * 4);
+  L.rec = (uint2*)take(rec * 8);
+  L.bytes = off;
+  return L;
+}
+
+// Stream owning global chunk (or group) x: the last stream whose first chunk
+// (group) is <= x. Streams without chunks share their successor's start and
+// are skipped by taking the last match.
+__device__ inline uint32_t owner_of_chunk(const Batch& b, uint32_t x) {
+  uint32_t s = 0;
+  for (uint32_t i = 1; i < b.k; ++i)
+    if (b.s[i].chunk_begin <= x) s = i;
+  return s;
+}
+
+__device__ inline uint32_t owner_of_group(const Batch& b, uint32_t x) {
+  uint32_t s = 0;
+  for (uint32_t i = 1; i < b.k; ++i)
+    if (b.s[i].group_begin <= x) s = i;
+  return s;
+}
+
+__device__ inline uint32_t bin_of(const Dims& d, uint32_t k, uint32_t host, uint32_t peer,
+                                  uint2& rec) {
+  const uint32_t m = fmix32(host ^ d.seed_mangle);
+  const uint32_t b = bit_of_peer(d, peer);
+  rec = make_uint2(m, b | (k << 31));
+  const uint32_t cs = m & low_mask(d.r);
+  return (k * d.S + cs) * d.R + (b >> 6);
+}
+
+__device__ inline uint32_t bin_of_record(const Dims& d, uint2 rec) {
+  const uint32_t k = rec.y >> 31;
+  const uint32_t b = rec.y & 0x7FFFFFFFu;
+  return (k * d.S + (rec.x & low_mask(d.r))) * d.R + (b >> 6);
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(kBlock) void k_histogram(Dims d, Batch b, uint32_t* counts) {
+  __shared__ uint32_t hist[kMaxBins];
+  const uint32_t gc = blockIdx.x;
+  const StreamDesc& st = b.s[owner_of_chunk(b, gc)];
+  for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) hist[i] = 0;
+  __syncthreads();
+  const uint64_t lo = (uint64_t)(gc - st.chunk_begin) * b.chunk;
+  const uint64_t hi = lo + b.chunk < st.n ? lo + b.chunk : st.n;
+  const int side = st.side;
+  for (uint64_t k0 = lo + threadIdx.x; k0 < hi; k0 += (uint64_t)kBlock * kUnroll) {
+    uint2 p[kUnroll];
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      const uint64_t k = k0 + (uint64_t)u * kBlock;
+      p[u] = k < hi ? st.pairs[k] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < kUnroll; ++u) {
+      if (k0 + (uint64_t)u * kBlock >= hi) break;
+      uint2 rec;
+      const uint32_t h0 = side == CBAA_SIDE_SRC ? p[u].x : p[u].y;
+      const uint32_t p0 = side == CBAA_SIDE_SRC ? p[u].y : p[u].x;
+      atomicAdd(&hist[bin_of(d, 0, h0, p0, rec)], 1u);
+      if (TWO) atomicAdd(&hist[bin_of(d, 1, p[u].y, p[u].x, rec)], 1u);
+    }
+  }
+  __syncthreads();
+  uint32_t* row = counts + (uint64_t)gc * b.nbins;
+  for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) row[i] = hist[i];
+}
+
+// Stream and chunk range [c0, c1) of global group g.
+__device__ inline uint32_t group_chunks(const Batch& b, uint32_t g, uint32_t& c0, uint32_t& c1) {
+  const uint32_t si = owner_of_group(b, g);
+  const StreamDesc& st = b.s[si];
+  const uint32_t nc = (uint32_t)((st.n + b.chunk - 1) / b.chunk);
+  c0 = st.chunk_begin + (g - st.group_begin) * kChunksPerGroup;
+  const uint32_t end = st.chunk_begin + nc;
+  c1 = c0 + kChunksPerGroup < end ? c0 + kChunksPerGroup : end;
+  return si;
+}
+
+__global__ __launch_bounds__(256) void k_group_sums(Batch b, const uint32_t* counts, uint32_t* gsum) {
+  const uint32_t bin = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t g = blockIdx.y;
+  if (bin >= b.nbins) return;
+  uint32_t c0, c1;
+  group_chunks(b, g, c0, c1);
+  uint32_t s = 0;
+  for (uint32_t c = c0; c < c1; ++c) s += counts[(uint64_t)c * b.nbins + bin];
+  gsum[(uint64_t)g * b.nbins + bin] = s;
+}
+
+// Exclusive scan of per-thread values over the block (kBlock threads).
+__device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_waves, uint32_t& total) {
+  const uint32_t lane = __lane_id();
+  const uint32_t wid = threadIdx.x / kWave;
+  uint32_t incl = v;
+#pragma unroll
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, kWave);
+    if (lane >= (uint32_t)o) incl += t;
+  }
+  __syncthreads();
+  if (lane == kWave - 1) lds_waves[wid] = incl;
+  __syncthreads();
+  uint32_t before = 0, tot = 0;
+  for (uint32_t w = 0; w < kBlock / kWave; ++w) {
+    if (w < wid) before += lds_waves[w];
+    tot += lds_waves[w];
+  }
+  total = tot;
+  __syncthreads();
+  return before + incl - v;
+}
+
+// Block si: bin totals of stream si (sum over its groups), then exclusive
+// prefixes over its bins of records (base) and apply segments (segpre).
+__global__ __launch_bounds__(kBlock) void k_bases(Batch b, const uint32_t* __restrict__ gsum,
+                                                  uint32_t* base, uint32_t* segpre) {
+  __shared__ uint32_t waves[kBlock / kWave];
+  __shared__ uint32_t carry_rec, carry_seg;
+  const uint32_t si = blockIdx.x;
+  const uint32_t g0 = b.s[si].group_begin;
+  const uint32_t g1 = si + 1 < b.k ? b.s[si + 1].group_begin : b.total_groups;
+  uint32_t* bs = base + (uint64_t)si * (b.nbins + 1);
+  uint32_t* sp = segpre + (uint64_t)si * (b.nbins + 1);
+  if (threadIdx.x == 0) {
+    carry_rec = 0;
+    carry_seg = 0;
+  }
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < b.nbins; b0 += kBlock) {
+    const uint32_t bin = b0 + threadIdx.x;
+    uint32_t tot = 0;
+    if (bin < b.nbins)
+      for (uint32_t g = g0; g < g1; ++g) tot += gsum[(uint64_t)g * b.nbins + bin];
+    const uint32_t nseg = (tot + b.seg - 1) / b.seg;
+    uint32_t sum_rec, sum_seg;
+    const uint32_t ex_rec = block_exclusive_scan(tot, waves, sum_rec);
+    const uint32_t ex_seg = block_exclusive_scan(nseg, waves, sum_seg);
+    const uint32_t cr = carry_rec, cg = carry_seg;
+    if (bin < b.nbins) {
+      bs[bin] = cr + ex_rec;
+      sp[bin] = cg + ex_seg;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      carry_rec = cr + sum_rec;
+      carry_seg = cg + sum_seg;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    bs[b.nbins] = carry_rec;
+    sp[b.nbins] = carry_seg;
+  }
+}
+
+__global__ void k_stream_items(Batch b, const uint32_t* segpre, uint32_t* items) {
+  if (threadIdx.x != 0) return;
+  uint32_t acc = 0;
+  for (uint32_t si = 0; si < b.k; ++si) {
+    items[si] = acc;
+    acc += segpre[(uint64_t)si * (b.nbins + 1) + b.nbins];
+  }
+  items[b.k] = acc;
+}
+
+// counts[c][bin] <- first record (inside the stream) of chunk c in bin.
+__global__ __launch_bounds__(256) void k_offsets(Batch b, uint32_t* counts,
+                                                 const uint32_t* __restrict__ gsum,
+                                                 const uint32_t* __restrict__ base) {
+  const uint32_t bin = blockIdx.x * 256 + threadIdx.x;
+  const uint32_t g = blockIdx.y;
+  if (bin >= b.nbins) return;
+  uint32_t c0, c1;
+  const uint32_t si = group_chunks(b, g, c0, c1);
+  uint32_t run = base[(uint64_t)si * (b.nbins + 1) + bin];
+  for (uint32_t h = b.s[si].group_begin; h < g; ++h) run += gsum[(uint64_t)h * b.nbins + bin];
+  uint32_t t[kChunksPerGroup];
+#pragma unroll
+  for (uint32_t i = 0; i < kChunksPerGroup; ++i)
+    t[i] = c0 + i < c1 ? counts[(uint64_t)(c0 + i) * b.nbins + bin] : 0u;
+#pragma unroll
+  for (uint32_t i = 0; i < kChunksPerGroup; ++i) {
+    if (c0 + i < c1) counts[(uint64_t)(c0 + i) * b.nbins + bin] = run;
+    run += t[i];
+  }
+}
+
+template <bool TWO>
+__global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b,
+                                                    const uint32_t* __restrict__ offsets,
+                                                    uint2* __restrict__ rec_all) {
+  constexpr uint32_t kPairsPerStep = TWO ? kStage / 2 : kStage;
+  constexpr int kPerThread = kPairsPerStep / kBlock;  // 8 (two cubes) or 16
+  constexpr int kRecs = TWO ? 2 * kPerThread : kPerThread;
+  __shared__ uint2 stage[kStage];
+  __shared__ uint32_t cursor[kMaxBins];
+  __shared__ uint32_t cnt[kMaxBins];
+  __shared__ uint32_t start[kMaxBins];
+  __shared__ uint32_t waves[kBlock / kWave];
+  const uint32_t gc = blockIdx.x;
+  const StreamDesc& st = b.s[owner_of_chunk(b, gc)];
+  uint2* rec = rec_all + st.rec_base;
+  const uint32_t* row = offsets + (uint64_t)gc * b.nbins;
+  for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) cursor[i] = row[i];
+  const uint64_t lo = (uint64_t)(gc - st.chunk_begin) * b.chunk;
+  const uint64_t hi = lo + b.chunk < st.n ? lo + b.chunk : st.n;
+  const int side = st.side;
+  for (uint64_t s0 = lo; s0 < hi; s0 += kPairsPerStep) {
+    for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) cnt[i] = 0;
+    __syncthreads();
+    uint2 r[kRecs];
+    uint32_t rank[kRecs];
+    uint2 p[kPerThread];
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+      const uint64_t k = s0 + threadIdx.x + (uint64_t)u * kBlock;
+      p[u] = k < hi ? st.pairs[k] : make_uint2(0u, 0u);
+    }
+#pragma unroll
+    for (int u = 0; u < kPerThread; ++u) {
+      const bool live = s0 + threadIdx.x + (uint64_t)u * kBlock < hi;
+      const uint32_t h0 = side == CBAA_SIDE_SRC ? p[u].x : p[u].y;
+      const uint32_t p0 = side == CBAA_SIDE_SRC ? p[u].y : p[u].x;
+      const int i0 = TWO ? 2 * u : u;
+      const uint32_t bn0 = bin_of(d, 0, h0, p0, r[i0]);
+      rank[i0] = live ? atomicAdd(&cnt[bn0], 1u) : 0xFFFFFFFFu;
+      if (TWO) {
+        const uint32_t bn1 = bin_of(d, 1, p[u].y, p[u].x, r[i0 + 1]);
+        rank[i0 + 1] = live ? atomicAdd(&cnt[bn1], 1u) : 0xFFFFFFFFu;
+      }
+    }
+    __syncthreads();
+    // exclusive prefix of the step's bin counts (nbins <= 2 * kBlock)
+    const uint32_t b0 = 2 * threadIdx.x;
+    const uint32_t c0 = b0 < b.nbins ? cnt[b0] : 0u;
+    const uint32_t c1 = b0 + 1 < b.nbins ? cnt[b0 + 1] : 0u;
+    uint32_t total;
+    const uint32_t ex = block_exclusive_scan(c0 + c1, waves, total);
+    if (b0 < b.nbins) start[b0] = ex;
+    if (b0 + 1 < b.nbins) start[b0 + 1] = ex + c0;
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < kRecs; ++i)
+      if (rank[i] != 0xFFFFFFFFu) stage[start[bin_of_record(d, r[i])] + rank[i]] = r[i];
+    __syncthreads();
+    for (uint32_t t = threadIdx.x; t < total; t += kBlock) {
+      const uint2 v = stage[t];
+      const uint32_t bn = bin_of_record(d, v);
+      rec[cursor[bn] + (t - start[bn])] = v;
+    }
+    __syncthreads();
+    for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) cursor[i] += cnt[i];
+    __syncthreads();
+  }
+}
+
+// Largest x in [0, n) with tab[x] <= v (tab ascending, tab[0] <= v < tab[n]).
+__device__ inline uint32_t upper_index(const uint32_t* tab, uint32_t n, uint32_t v) {
+  uint32_t lo = 0, hi = n;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) / 2;
+    if (tab[mid] <= v) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+template <int NRA, int NVA>
+__global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* __restrict__ rec_all,
+                                                  const uint32_t* __restrict__ base,
+                                                  const uint32_t* __restrict__ segpre,
+                                                  const uint32_t* __restrict__ items) {
+  __shared__ uint64_t tile[kMaxTileWords];
+  uint32_t* tile32 = (uint32_t*)tile;
+  const uint32_t n_items = items[b.k];
+  const uint32_t per_cube = d.S * d.R;
+  for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+    const uint32_t si = upper_index(items, b.k, item);
+    const StreamDesc& st = b.s[si];
+    const uint32_t* bs = base + (uint64_t)si * (b.nbins + 1);
+    const uint32_t* sp = segpre + (uint64_t)si * (b.nbins + 1);
+    const uint32_t local = item - items[si];
+    const uint32_t bin = upper_index(sp, b.nbins, local);
+    const uint32_t seg = local - sp[bin];
+    const uint32_t r0 = bs[bin] + seg * b.seg;
+    const uint32_t r1 = r0 + b.seg < bs[bin + 1] ? r0 + b.seg : bs[bin + 1];
+    const uint2* rec = rec_all + st.rec_base;
+    for (uint32_t w = threadIdx.x; w < d.W; w += kBlock) tile[w] = 0;
+    __syncthreads();
+    for (uint32_t i0 = r0 + threadIdx.x; i0 < r1; i0 += kBlock * kApplyUnroll) {
+      uint2 rr[kApplyUnroll];
+#pragma unroll
+      for (int u = 0; u < kApplyUnroll; ++u) {
+        const uint32_t i = i0 + u * kBlock;
+        rr[u] = i < r1 ? rec[i] : make_uint2(0u, 0u);
+      }
+#pragma unroll
+      for (int u = 0; u < kApplyUnroll; ++u) {
+        if (i0 + u * kBlock >= r1) break;
+        const uint2 r = rr[u];
+        const uint32_t lp = r.x >> d.r;
+        const uint32_t half = (r.y >> 5) & 1u;
+        const uint32_t mask = 1u << (r.y & 31u);
+#pragma unroll
+        for (int a = 0; a < NRA; ++a) {
+          const uint32_t slot = d.aoff[a] + (rotr_in(lp, d.off[a], d.L) & low_mask(d.cbn[a]));
+          atomicOr(&tile32[2 * slot + half], mask);
+        }
+#pragma unroll
+        for (int j = 0; j < NVA; ++j) {
+          const uint32_t slot = d.aoff[NRA + j] + va_col(d, j, lp);
+          atomicOr(&tile32[2 * slot + half], mask);
+        }
+      }
+    }
+    __syncthreads();
+    uint64_t* cube = bin < per_cube ? st.cube0 : st.cube1;
+    const uint32_t row = bin < per_cube ? bin : bin - per_cube;  // = cs * R + rb
+    uint64_t* dst = cube + (uint64_t)row * d.W;
+    for (uint32_t w = threadIdx.x; w < d.W; w += kBlock) {
+      const uint64_t v = tile[w];
+      if (v) __hip_atomic_fetch_or(dst + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    __syncthreads();
+  }
+}
+
+int check(const char* what) {
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CBAA_OK : hip_fail(e, what);
+}
+
+template <int NRA, int NVA>
+int apply_dispatch(const Dims& d, const Batch& b, const Layout& L, uint32_t blocks, hipStream_t s) {
+  hipLaunchKernelGGL((k_apply<NRA, NVA>), dim3(blocks), dim3(kBlock), 0, s, d, b, L.rec, L.base,
+                     L.segpre, L.items);
+  return check("apply launch");
+}
+
+int run_apply(const Dims& d, const Batch& b, const Layout& L, uint32_t blocks, hipStream_t s) {
+#define CBAA_APPLY(NRA, NVA) \
+  if (d.n_ra == NRA && d.n_va == NVA) return apply_dispatch<NRA, NVA>(d, b, L, blocks, s);
+  CBAA_APPLY(2, 0) CBAA_APPLY(2, 1) CBAA_APPLY(2, 2)
+  CBAA_APPLY(3, 0) CBAA_APPLY(3, 1) CBAA_APPLY(3, 2)
+  CBAA_APPLY(4, 0) CBAA_APPLY(4, 1) CBAA_APPLY(4, 2)
+#undef CBAA_APPLY
+  return CBAA_ECONFIG;
+}
+
+template <bool TWO>
+int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStream_t s) {
+  int rc;
+  if (b.total_chunks == 0) return CBAA_OK;
+  hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.counts);
+  if ((rc = check("histogram launch")) != CBAA_OK) return rc;
+  const dim3 sgrid((b.nbins + 255) / 256, b.total_groups);
+  hipLaunchKernelGGL(k_group_sums, sgrid, dim3(256), 0, s, b, L.counts, L.gsum);
+  if ((rc = check("group sums launch")) != CBAA_OK) return rc;
+  hipLaunchKernelGGL(k_bases, dim3(b.k), dim3(kBlock), 0, s, b, L.gsum, L.base, L.segpre);
+  if ((rc = check("bases launch")) != CBAA_OK) return rc;
+  hipLaunchKernelGGL(k_stream_items, dim3(1), dim3(64), 0, s, b, L.segpre, L.items);
+  if ((rc = check("items launch")) != CBAA_OK) return rc;
+  hipLaunchKernelGGL(k_offsets, sgrid, dim3(256), 0, s, b, L.counts, L.gsum, L.base);
+  if ((rc = check("offsets launch")) != CBAA_OK) return rc;
+  hipLaunchKernelGGL((k_scatter<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.counts,
+                     L.rec);
+  if ((rc = check("scatter launch")) != CBAA_OK) return rc;
+  return run_apply(d, b, L, apply_blocks, s);
+}
+
+}  // namespace
+
+bool partitioned_supported(const Dims& d) {
+  // LDS tile of one row block of a sketch; bins of two cubes in LDS counters
+  return d.W <= kMaxTileWords && 2u * d.S * d.R <= kMaxBins;
+}
+
+bool tuning_valid(const cbaa_tuning* t) {
+  if (!t) return true;
+  const Tuning r = effective(t);
+  return r.chunk >= 1024 && r.chunk <= (1u << 22) && r.chunk % 1024 == 0 && r.seg >= 1024 &&
+         r.apply_blocks >= 1 && r.apply_blocks <= 65536;
+}
+
+uint64_t batch_scratch_bytes(const Dims& d, const StreamSpec* specs, int k, int n_cubes,
+                             const cbaa_tuning* t) {
+  Batch b;
+  b.k = (uint32_t)k;
+  for (int i = 0; i < k; ++i) b.s[i].n = specs[i].n;
+  return plan(d, n_cubes, effective(t).chunk, b, nullptr).bytes;
+}
+
+int launch_update_batch(const Dims& d, const StreamSpec* specs, int k, int n_cubes,
+                        const cbaa_tuning* t, void* scratch, hipStream_t s) {
+  const Tuning tu = effective(t);
+  Batch b;
+  b.k = (uint32_t)k;
+  b.seg = tu.seg;
+  for (int i = 0; i < k; ++i) {
+    b.s[i].pairs = (const uint2*)specs[i].pairs;
+    b.s[i].n = specs[i].n;
+    b.s[i].cube0 = specs[i].cube0;
+    b.s[i].cube1 = specs[i].cube1;
+    b.s[i].side = (uint32_t)specs[i].side;
+    b.s[i].pad = 0;
+  }
+  const Layout L = plan(d, n_cubes, tu.chunk, b, scratch);
+  return n_cubes == 2 ? run<true>(d, b, L, tu.apply_blocks, s)
+                      : run<false>(d, b, L, tu.apply_blocks, s);
+}
+
+uint64_t partitioned_scratch_bytes(const Dims& d, uint64_t n_pairs, int n_cubes) {
+  StreamSpec sp{};
+  const uint64_t nb = n_pairs == 0 ? 1 : n_pairs;
+  const uint64_t cap = (0xFFFFFFFFull / (uint64_t)n_cubes) / kDefaultChunk * kDefaultChunk;
+  sp.n = nb > cap ? cap : nb;
+  return batch_scratch_bytes(d, &sp, 1, n_cubes, nullptr);
+}
+
+uint64_t partitioned_min_scratch_bytes(const Dims& d, int n_cubes, uint64_t n_pairs) {
+  StreamSpec sp{};
+  sp.n = n_pairs < kDefaultChunk ? n_pairs : kDefaultChunk;
+  return batch_scratch_bytes(d, &sp, 1, n_cubes, nullptr);
+}
+
 int launch_update_partitioned(const Dims& d, uint64_t* c0, uint64_t* c1, const uint32_t* pairs,
-                              uint64_t n, int side, void*, uint64_t, hipStream_t s) {
-  return launch_update_direct(d, c0, c1, pairs, n, side, s);
+                              uint64_t n, int side, void* scratch, uint64_t scratch_bytes,
+                              hipStream_t s) {
+  const int nc = c1 ? 2 : 1;
+  const uint64_t chunk = kDefaultChunk;
+  // largest batch (whole chunks) that fits the scratch; a stream's records are
+  // addressed with 32-bit offsets
+  const uint64_t cap = (0xFFFFFFFFull / (uint64_t)nc) / chunk * chunk;
+  auto bytes_for = [&](uint64_t m) {
+    StreamSpec sp{};
+    sp.n = m;
+    return batch_scratch_bytes(d, &sp, 1, nc, nullptr);
+  };
+  uint64_t nb;
+  if (n <= cap && bytes_for(n) <= scratch_bytes) {
+    nb = n;
+  } else {
+    uint64_t lo = 1, hi = (n + chunk - 1) / chunk;  // in chunks
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi + 1) / 2;
+      if (mid * chunk <= cap && bytes_for(mid * chunk) <= scratch_bytes) lo = mid;
+      else hi = mid - 1;
+    }
+    nb = lo * chunk;
+  }
+  for (uint64_t off = 0; off < n; off += nb) {
+    StreamSpec sp{};
+    sp.pairs = pairs + 2 * off;
+    sp.n = n - off < nb ? n - off : nb;
+    sp.cube0 = c0;
+    sp.cube1 = c1;
+    sp.side = c1 ? CBAA_SIDE_SRC : side;
+    const int rc = launch_update_batch(d, &sp, 1, nc, nullptr, scratch, s);
+    if (rc != CBAA_OK) return rc;
+  }
+  return CBAA_OK;
 }
 
 }  // namespace cbaa

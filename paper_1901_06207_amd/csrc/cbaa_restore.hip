@@ -62,124 +62,121 @@ __device__ inline uint32_t lane_id() { return __lane_id(); }
 
 // ---- per-column zero counts ---------------------------------------------
 // Thread (cs, w..w+1): popcounts of two neighbouring columns' words over all
-// R row blocks; a wave reads 1 KiB contiguous per row block.
+// R row blocks (16 loads in flight); a wave reads 1 KiB contiguous per row
+// block. Each array's one-bit total is accumulated into ones[cs][a] (zeroed
+// beforehand) through an LDS partial per block.
 __global__ __launch_bounds__(kScanBlock) void k_column_zeros(Dims d, const uint4* __restrict__ cube,
-                                                             uint32_t* __restrict__ zeros2) {
+                                                             uint32_t* __restrict__ zeros2,
+                                                             uint32_t* __restrict__ ones) {
+  __shared__ uint32_t part[CBAA_MAX_ARRAYS];
   const uint32_t cs = blockIdx.y;
+  if (threadIdx.x < CBAA_MAX_ARRAYS) part[threadIdx.x] = 0;
+  __syncthreads();
   const uint32_t pair = blockIdx.x * kScanBlock + threadIdx.x;  // column pair index
   const uint32_t half_w = d.W / 2;
-  if (pair >= half_w) return;
-  uint32_t c0 = 0, c1 = 0;
-  const uint4* p = cube + ((uint64_t)cs * d.R) * half_w + pair;
-  uint32_t rb = 0;
-  for (; rb + 4 <= d.R; rb += 4) {
-    const uint4 v0 = p[(uint64_t)(rb + 0) * half_w];
-    const uint4 v1 = p[(uint64_t)(rb + 1) * half_w];
-    const uint4 v2 = p[(uint64_t)(rb + 2) * half_w];
-    const uint4 v3 = p[(uint64_t)(rb + 3) * half_w];
-    c0 += __popc(v0.x) + __popc(v0.y) + __popc(v1.x) + __popc(v1.y) + __popc(v2.x) + __popc(v2.y) +
-          __popc(v3.x) + __popc(v3.y);
-    c1 += __popc(v0.z) + __popc(v0.w) + __popc(v1.z) + __popc(v1.w) + __popc(v2.z) + __popc(v2.w) +
-          __popc(v3.z) + __popc(v3.w);
-  }
-  for (; rb < d.R; ++rb) {
-    uint4 v = p[(uint64_t)rb * half_w];
-    c0 += __popc(v.x) + __popc(v.y);
-    c1 += __popc(v.z) + __popc(v.w);
-  }
-  zeros2[(uint64_t)cs * half_w + pair] = (d.g - c0) | ((d.g - c1) << 16);
-}
-
-// Block-wide sum of per-thread counts (each below 2^32 in total per wave).
-__device__ inline uint64_t block_sum(uint32_t v, uint64_t* lds) {
-  const uint32_t w = wave_sum(v);
-  const int wid = threadIdx.x / kWave;
-  __syncthreads();
-  if (lane_id() == 0) lds[wid] = w;
-  __syncthreads();
-  uint64_t t = 0;
-  for (int i = 0; i < (int)(blockDim.x / kWave); ++i) t += lds[i];
-  __syncthreads();
-  return t;
-}
-
-// One block per sketch: array fills, eps (Thm. 1 with measured fills), Zmax,
-// and, if `lists`, the ascending hot-column list of every RA (Alg. 2).
-__global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* __restrict__ zeros,
-                                                        uint32_t* ones, double* eps, int32_t* zmax,
-                                                        uint32_t* hcnt, uint16_t* hot, double x,
-                                                        int rule, int lists,
-                                                        cbaa_restore_stats* stats) {
-  __shared__ uint64_t red[kPrepBlock / kWave];
-  __shared__ uint32_t wave_cnt[kPrepBlock / kWave];
-  __shared__ int32_t s_zmax;
-  __shared__ uint64_t s_ones[CBAA_MAX_ARRAYS];
-  const uint32_t cs = blockIdx.x;
-  const uint16_t* z = zeros + (uint64_t)cs * d.W;
-
-  for (uint32_t a = 0; a < d.A; ++a) {
-    uint32_t zs = 0;  // at most 64 columns of at most 2^15 zeros per thread
-    for (uint32_t j = threadIdx.x; j < d.ncol[a]; j += blockDim.x) zs += z[d.aoff[a] + j];
-    const uint64_t tot = block_sum(zs, red);
-    if (threadIdx.x == 0) s_ones[a] = (uint64_t)d.ncol[a] * d.g - tot;
-  }
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    const double g = (double)d.g;
-    double e = 1.0;
-    for (uint32_t a = 0; a < d.A; ++a) {
-      ones[cs * d.A + a] = (uint32_t)s_ones[a];
-      e = e * ((double)s_ones[a] / ((double)d.ncol[a] * g));
+  if (pair < half_w) {
+    uint32_t c0 = 0, c1 = 0;
+    const uint4* p = cube + ((uint64_t)cs * d.R) * half_w + pair;
+    uint32_t rb = 0;
+    constexpr uint32_t kU = 16;
+    for (; rb + kU <= d.R; rb += kU) {
+      uint4 v[kU];
+#pragma unroll
+      for (uint32_t u = 0; u < kU; ++u) v[u] = p[(uint64_t)(rb + u) * half_w];
+#pragma unroll
+      for (uint32_t u = 0; u < kU; ++u) {
+        c0 += __popc(v[u].x) + __popc(v[u].y);
+        c1 += __popc(v[u].z) + __popc(v[u].w);
+      }
     }
-    double zf;
-    if (rule == CBAA_THR_PAPER)
-      zf = (g + g * e) * x - g * e;
-    else
-      zf = (g - g * e) * x;
-    const int32_t zm = zf < 0.0 ? -1 : (int32_t)floor(zf);
-    if (eps) eps[cs] = e;
-    if (zmax) zmax[cs] = zm;
-    s_zmax = zm;
+    for (; rb < d.R; ++rb) {
+      const uint4 v = p[(uint64_t)rb * half_w];
+      c0 += __popc(v.x) + __popc(v.y);
+      c1 += __popc(v.z) + __popc(v.w);
+    }
+    zeros2[(uint64_t)cs * half_w + pair] = (d.g - c0) | ((d.g - c1) << 16);
+    // both columns lie in one array: array offsets are even
+    const uint32_t w = 2 * pair;
+    uint32_t a = 0;
+    while (a + 1 < d.A && w >= d.aoff[a + 1]) ++a;
+    atomicAdd(&part[a], c0 + c1);
   }
   __syncthreads();
-  if (!lists) return;
-  const int32_t zm = s_zmax;
+  if (threadIdx.x < d.A && part[threadIdx.x])
+    atomicAdd(&ones[cs * d.A + threadIdx.x], part[threadIdx.x]);
+}
+
+// Per-sketch eps (Thm. 1 with the measured fills) and Zmax, in fp64 with the
+// operations in the order the oracle uses.
+__device__ inline int32_t sketch_threshold(const Dims& d, const uint32_t* ones, uint32_t cs,
+                                           double x, int rule, double* eps_out) {
+  const double g = (double)d.g;
+  double e = 1.0;
+  for (uint32_t a = 0; a < d.A; ++a)
+    e = e * ((double)ones[cs * d.A + a] / ((double)d.ncol[a] * g));
+  double zf;
+  if (rule == CBAA_THR_PAPER)
+    zf = (g + g * e) * x - g * e;
+  else
+    zf = (g - g * e) * x;
+  *eps_out = e;
+  return zf < 0.0 ? -1 : (int32_t)floor(zf);
+}
+
+// Block (cs, i): Zmax of sketch cs and the ascending hot-column list of RA i
+// (Alg. 2) by ordered ballot compaction. Block (cs, 0) also stores eps, Zmax.
+__global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* __restrict__ zeros,
+                                                        const uint32_t* __restrict__ ones,
+                                                        double* eps, int32_t* zmax, uint32_t* hcnt,
+                                                        uint16_t* hot, double x, int rule,
+                                                        cbaa_restore_stats* stats) {
+  __shared__ uint32_t wave_cnt[kPrepBlock / kWave];
+  const uint32_t cs = blockIdx.x;
+  const uint32_t i = blockIdx.y;
+  double e;
+  const int32_t zm = sketch_threshold(d, ones, cs, x, rule, &e);
+  if (i == 0 && threadIdx.x == 0) {
+    eps[cs] = e;
+    zmax[cs] = zm;
+  }
+  if (!hot) return;
+  const uint16_t* z = zeros + (uint64_t)cs * d.W + d.aoff[i];
   const int wid = threadIdx.x / kWave;
   const int nw = blockDim.x / kWave;
-  uint64_t hot_total = 0;
-  for (uint32_t i = 0; i < d.n_ra; ++i) {
-    uint16_t* out = hot + ((uint64_t)cs * d.n_ra + i) * d.maxc_ra;
-    uint32_t base = 0;
-    for (uint32_t t0 = 0; t0 < d.ncol[i]; t0 += blockDim.x) {
-      const uint32_t j = t0 + threadIdx.x;
-      const bool pred = j < d.ncol[i] && (int32_t)z[d.aoff[i] + j] <= zm;
-      const uint64_t bal = __ballot(pred);
-      const uint32_t before = __popcll(bal & ((1ull << lane_id()) - 1ull));
-      if (lane_id() == 0) wave_cnt[wid] = __popcll(bal);
-      __syncthreads();
-      uint32_t woff = 0, total = 0;
-      for (int w = 0; w < nw; ++w) {
-        if (w < wid) woff += wave_cnt[w];
-        total += wave_cnt[w];
-      }
-      if (pred) out[base + woff + before] = (uint16_t)j;
-      base += total;
-      __syncthreads();
+  uint16_t* out = hot + ((uint64_t)cs * d.n_ra + i) * d.maxc_ra;
+  uint32_t base = 0;
+  for (uint32_t t0 = 0; t0 < d.ncol[i]; t0 += blockDim.x) {
+    const uint32_t j = t0 + threadIdx.x;
+    const bool pred = j < d.ncol[i] && (int32_t)z[j] <= zm;
+    const uint64_t bal = __ballot(pred);
+    const uint32_t before = __popcll(bal & ((1ull << lane_id()) - 1ull));
+    if (lane_id() == 0) wave_cnt[wid] = __popcll(bal);
+    __syncthreads();
+    uint32_t woff = 0, total = 0;
+    for (int w = 0; w < nw; ++w) {
+      if (w < wid) woff += wave_cnt[w];
+      total += wave_cnt[w];
     }
-    if (threadIdx.x == 0) hcnt[cs * d.n_ra + i] = base;
-    hot_total += base;
+    if (pred) out[base + woff + before] = (uint16_t)j;
+    base += total;
+    __syncthreads();
   }
-  if (threadIdx.x == 0 && stats)
-    __hip_atomic_fetch_add(&stats->hot_columns, hot_total, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  if (threadIdx.x == 0) {
+    hcnt[cs * d.n_ra + i] = base;
+    if (stats)
+      __hip_atomic_fetch_add(&stats->hot_columns, (uint64_t)base, __ATOMIC_RELAXED,
+                             __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
-__global__ void k_reset_stats(cbaa_restore_stats* st) {
-  if (threadIdx.x == 0) {
+__global__ void k_reset(cbaa_restore_stats* st, uint32_t* ones, uint32_t n_ones) {
+  if (st && threadIdx.x == 0) {
     st->n_hosts = 0;
     st->hot_columns = 0;
     st->partial_checked = 0;
     st->tuples_checked = 0;
   }
+  for (uint32_t i = threadIdx.x; i < n_ones; i += blockDim.x) ones[i] = 0;
 }
 
 // ---- tuple join and union-column verification (Alg. 3) ------------------
@@ -257,16 +254,19 @@ __device__ inline void emit_host(const Dims& d, const JoinArgs& ja, uint32_t cs,
   }
 }
 
+// Candidates that pass the CP screen are taken kBatch at a time so their
+// column loads are in flight together.
+constexpr int kBatch = 4;
+
 template <int NRA, int NVA, int RPL, int LEVEL>
 __device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t zm,
                        uint32_t (&t)[NRA], const Col<RPL>& acc, uint32_t& n_partial,
                        uint32_t& n_tuples) {
   const uint32_t cnt = ja.hcnt[cs * NRA + LEVEL];
   const uint16_t* list = ja.hot + ((uint64_t)cs * NRA + LEVEL) * d.maxc_ra;
-  const uint32_t prev = t[LEVEL - 1];
-  const uint32_t want_lo = prev >> d.ep[LEVEL - 1];          // CP of hc_{l-1}
+  const uint32_t want_lo = t[LEVEL - 1] >> d.ep[LEVEL - 1];   // CP of hc_{l-1}
   const uint32_t cp_mask = low_mask(d.cp[LEVEL - 1]);
-  const uint32_t want_hi = t[0] & low_mask(d.cp[NRA - 1]);   // first bits of hc_0
+  const uint32_t want_hi = t[0] & low_mask(d.cp[NRA - 1]);    // first bits of hc_0
   for (uint32_t base = 0; base < cnt; base += kWave) {
     const uint32_t j = base + lane_id();
     const uint32_t cand = j < cnt ? list[j] : 0u;
@@ -274,33 +274,48 @@ __device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t z
     if (LEVEL == NRA - 1) ok = ok && (cand >> d.ep[LEVEL]) == want_hi;
     uint64_t m = __ballot(ok);
     while (m) {
-      const int l = __builtin_ctzll(m);
-      m &= m - 1;
-      const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)cand, l);
-      Col<RPL> c;
-      load_col<RPL>(d, ja.cube, cs, d.aoff[LEVEL] + h, c);
+      uint32_t h[kBatch];
+      int nb = 0;
 #pragma unroll
-      for (int q = 0; q < RPL; ++q) c.w[q] &= acc.w[q];
-      t[LEVEL] = h;
-      if constexpr (LEVEL < NRA - 1) {
-        ++n_partial;
-        if ((int32_t)col_zeros<RPL>(d, c) > zm) continue;
-        extend<NRA, NVA, RPL, LEVEL + 1>(d, ja, cs, zm, t, c, n_partial, n_tuples);
-      } else {
-        // complete CP-valid tuple: LP = concatenation of the EPs
-        uint32_t lp = 0;
-#pragma unroll
-        for (int i = 0; i < NRA; ++i) lp |= rotl_in(t[i] & low_mask(d.ep[i]), d.off[i], d.L);
-#pragma unroll
-        for (int v = 0; v < NVA; ++v) {
-          Col<RPL> vc;
-          load_col<RPL>(d, ja.cube, cs, d.aoff[NRA + v] + va_col(d, v, lp), vc);
-#pragma unroll
-          for (int q = 0; q < RPL; ++q) c.w[q] &= vc.w[q];
+      for (int q = 0; q < kBatch; ++q) {
+        h[q] = 0;
+        if (m) {
+          const int l = __builtin_ctzll(m);
+          m &= m - 1;
+          h[q] = (uint32_t)__builtin_amdgcn_readlane((int)cand, l);
+          nb = q + 1;
         }
-        ++n_tuples;
-        const uint32_t z = col_zeros<RPL>(d, c);
-        if ((int32_t)z <= zm) emit_host<NRA, NVA>(d, ja, cs, lp, z);
+      }
+      Col<RPL> c[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+        if (q < nb) load_col<RPL>(d, ja.cube, cs, d.aoff[LEVEL] + h[q], c[q]);
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) {
+        if (q >= nb) break;
+#pragma unroll
+        for (int r = 0; r < RPL; ++r) c[q].w[r] &= acc.w[r];
+        t[LEVEL] = h[q];
+        if constexpr (LEVEL < NRA - 1) {
+          ++n_partial;
+          if ((int32_t)col_zeros<RPL>(d, c[q]) > zm) continue;
+          extend<NRA, NVA, RPL, LEVEL + 1>(d, ja, cs, zm, t, c[q], n_partial, n_tuples);
+        } else {
+          // complete CP-valid tuple: LP = concatenation of the EPs
+          uint32_t lp = 0;
+#pragma unroll
+          for (int i = 0; i < NRA; ++i) lp |= rotl_in(t[i] & low_mask(d.ep[i]), d.off[i], d.L);
+#pragma unroll
+          for (int v = 0; v < NVA; ++v) {
+            Col<RPL> vc;
+            load_col<RPL>(d, ja.cube, cs, d.aoff[NRA + v] + va_col(d, v, lp), vc);
+#pragma unroll
+            for (int r = 0; r < RPL; ++r) c[q].w[r] &= vc.w[r];
+          }
+          ++n_tuples;
+          const uint32_t z = col_zeros<RPL>(d, c[q]);
+          if ((int32_t)z <= zm) emit_host<NRA, NVA>(d, ja, cs, lp, z);
+        }
       }
     }
   }
@@ -360,29 +375,16 @@ __global__ __launch_bounds__(kSortBlock) void k_sort_chunks(const cbaa_host* sta
   const uint64_t n = stats->n_hosts < capacity ? stats->n_hosts : capacity;
   const uint64_t base = (uint64_t)blockIdx.x * kSortChunk;
   if (base >= n) return;
-  for (int i = threadIdx.x; i < kSortChunk; i += kSortBlock) {
-    const uint64_t g = base + i;
-    k[i] = g < n ? (((uint64_t)stage[g].ip << 32) | (uint32_t)g) : ~0ull;
-  }
+  const uint32_t m = (uint32_t)(n - base < kSortChunk ? n - base : kSortChunk);
+  for (uint32_t i = threadIdx.x; i < m; i += kSortBlock)
+    k[i] = ((uint64_t)stage[base + i].ip << 32) | (uint32_t)(base + i);
   __syncthreads();
-  for (int size = 2; size <= kSortChunk; size <<= 1) {
-    for (int stride = size >> 1; stride > 0; stride >>= 1) {
-      for (int i = threadIdx.x; i < kSortChunk / 2; i += kSortBlock) {
-        const int lo = 2 * i - (i & (stride - 1));
-        const int hi = lo + stride;
-        const bool up = (lo & size) == 0;
-        const uint64_t a = k[lo], b = k[hi];
-        if ((a > b) == up) {
-          k[lo] = b;
-          k[hi] = a;
-        }
-      }
-      __syncthreads();
-    }
-  }
-  for (int i = threadIdx.x; i < kSortChunk; i += kSortBlock) {
-    const uint64_t g = base + i;
-    if (g < n) keys[g] = k[i];
+  // keys are distinct: the rank of a key is the number of smaller keys
+  for (uint32_t i = threadIdx.x; i < m; i += kSortBlock) {
+    const uint64_t key = k[i];
+    uint32_t rank = 0;
+    for (uint32_t j = 0; j < m; ++j) rank += k[j] < key ? 1u : 0u;
+    keys[base + rank] = key;
   }
 }
 
@@ -447,16 +449,66 @@ __global__ __launch_bounds__(256) void k_estimate(Dims d, const uint64_t* __rest
   }
 }
 
+// Features of the learned estimator, in the log domain of the linear count:
+// for each array a, f_a = ln(1 + g * u_a) with u_a = -ln(max(z_a, 1) / g)
+// (z_a = zeros of the host's column of array a, so g * u_a is that column's
+// own linear count); optionally the same for the union column with Thm. 2's
+// correction, u = max(0, -ln(max(Z, 1) / (g - g*eps))), and g * eps.
+__device__ inline float log_count_feature(double g, uint32_t z, double denom) {
+  double u = -log((double)(z == 0 ? 1u : z) / denom);
+  if (u < 0.0) u = 0.0;
+  return (float)log1p(g * u);
+}
+
+template <int NRA, int NVA, int RPL>
+__global__ __launch_bounds__(256) void k_features(Dims d, const uint64_t* __restrict__ cube,
+                                                  const uint32_t* __restrict__ hosts, uint64_t n,
+                                                  const double* __restrict__ eps, uint32_t F,
+                                                  float* x) {
+  constexpr int A = NRA + NVA;
+  const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
+  const uint64_t nw = ((uint64_t)gridDim.x * blockDim.x) / kWave;
+  const double g = (double)d.g;
+  for (uint64_t k = gw; k < n; k += nw) {
+    uint32_t slot[A];
+    const uint32_t cs = host_slots<NRA, NVA>(d, hosts[k], slot);
+    Col<RPL> u;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) u.w[q] = ~0ull;
+#pragma unroll
+    for (int a = 0; a < A; ++a) {
+      Col<RPL> c;
+      load_col<RPL>(d, cube, cs, slot[a], c);
+      const uint32_t za = col_zeros<RPL>(d, c);
+      if (lane_id() == 0) x[k * F + a] = log_count_feature(g, za, g);
+#pragma unroll
+      for (int q = 0; q < RPL; ++q) u.w[q] &= c.w[q];
+    }
+    const uint32_t z = col_zeros<RPL>(d, u);
+    if (lane_id() == 0 && F == (uint32_t)A + 2) {
+      const double e = eps[cs];
+      x[k * F + A] = log_count_feature(g, z, g - g * e);
+      x[k * F + A + 1] = (float)(g * e);
+    }
+  }
+}
+
 int check_launch(const char* what) {
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CBAA_OK : hip_fail(e, what);
 }
 
-int run_scan(const Dims& d, const uint64_t* cube, uint16_t* zeros, hipStream_t s) {
+// Zeroes the counters (stats may be null) and the fill accumulators, then
+// scans the cube.
+int run_scan(const Dims& d, const uint64_t* cube, uint16_t* zeros, uint32_t* ones,
+             cbaa_restore_stats* stats, hipStream_t s) {
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, stats, ones, d.S * d.A);
+  int rc = check_launch("reset launch");
+  if (rc != CBAA_OK) return rc;
   const uint32_t half_w = d.W / 2;
   dim3 grid((half_w + kScanBlock - 1) / kScanBlock, d.S);
   hipLaunchKernelGGL(k_column_zeros, grid, dim3(kScanBlock), 0, s, d, (const uint4*)cube,
-                     (uint32_t*)zeros);
+                     (uint32_t*)zeros, ones);
   return check_launch("column scan launch");
 }
 
@@ -509,6 +561,27 @@ int run_join(const Dims& d, const JoinArgs& ja, hipStream_t s) {
   CBAA_ARRAY_DISPATCH(dispatch_rpl_join, d, ja, s);
 }
 
+template <int NRA, int NVA>
+int dispatch_rpl_feat(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
+                      const double* eps, uint32_t F, float* x, hipStream_t s) {
+  uint64_t blocks = (n + 3) / 4;
+  if (blocks > 4096) blocks = 4096;
+#define CBAA_FEAT(RPL)                                                                       \
+  if (d.R <= RPL * kWave) {                                                                  \
+    hipLaunchKernelGGL((k_features<NRA, NVA, RPL>), dim3((uint32_t)blocks), dim3(256), 0, s, \
+                       d, cube, hosts, n, eps, F, x);                                        \
+    return check_launch("features launch");                                                 \
+  }
+  CBAA_FEAT(1) CBAA_FEAT(2) CBAA_FEAT(4) CBAA_FEAT(8)
+#undef CBAA_FEAT
+  return CBAA_ECONFIG;
+}
+
+int run_feat(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
+             const double* eps, uint32_t F, float* x, hipStream_t s) {
+  CBAA_ARRAY_DISPATCH(dispatch_rpl_feat, d, cube, hosts, n, eps, F, x, s);
+}
+
 int run_est(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
             const double* eps, double* est, uint16_t* zeros, uint16_t* layer, hipStream_t s) {
   CBAA_ARRAY_DISPATCH(dispatch_rpl_est, d, cube, hosts, n, eps, est, zeros, layer, s);
@@ -522,24 +595,16 @@ uint64_t restore_scratch_bytes(const Dims& d, uint64_t capacity) {
 
 int launch_column_zeros(const Dims& d, const uint64_t* cube, uint16_t* zeros, uint32_t* ones,
                         hipStream_t s) {
-  int rc = run_scan(d, cube, zeros, s);
-  if (rc != CBAA_OK) return rc;
-  // array fills only: no threshold, no hot lists
-  hipLaunchKernelGGL(k_prepare, dim3(d.S), dim3(kPrepBlock), 0, s, d, zeros, ones,
-                     (double*)nullptr, (int32_t*)nullptr, (uint32_t*)nullptr,
-                     (uint16_t*)nullptr, 1.0, 0, 0, (cbaa_restore_stats*)nullptr);
-  return check_launch("fill reduction launch");
+  return run_scan(d, cube, zeros, ones, nullptr, s);
 }
 
 int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void* scratch,
                    uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s) {
   RestoreScratch rs = carve(d, scratch, capacity);
-  hipLaunchKernelGGL(k_reset_stats, dim3(1), dim3(64), 0, s, stats);
-  int rc = check_launch("reset launch");
-  if (rc == CBAA_OK) rc = run_scan(d, cube, rs.zeros, s);
+  int rc = run_scan(d, cube, rs.zeros, rs.ones, stats, s);
   if (rc != CBAA_OK) return rc;
-  hipLaunchKernelGGL(k_prepare, dim3(d.S), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones, rs.eps,
-                     rs.zmax, rs.hcnt, rs.hot, x, rule, 1, stats);
+  hipLaunchKernelGGL(k_prepare, dim3(d.S, d.n_ra), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
+                     rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
   JoinArgs ja{cube, rs.hot, rs.hcnt, rs.zmax, rs.eps, rs.stage, capacity, stats};
   if ((rc = run_join(d, ja, s)) != CBAA_OK) return rc;
@@ -557,13 +622,25 @@ int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, 
                     double* est, uint16_t* zeros, uint16_t* layer_zeros, void* scratch,
                     hipStream_t s) {
   RestoreScratch rs = carve(d, scratch, 0);
-  int rc = run_scan(d, cube, rs.zeros, s);
+  int rc = run_scan(d, cube, rs.zeros, rs.ones, nullptr, s);
   if (rc != CBAA_OK) return rc;
-  hipLaunchKernelGGL(k_prepare, dim3(d.S), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones, rs.eps,
-                     rs.zmax, rs.hcnt, rs.hot, 1.0, CBAA_THR_THM2, 0,
+  hipLaunchKernelGGL(k_prepare, dim3(d.S, 1), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
+                     rs.eps, rs.zmax, rs.hcnt, (uint16_t*)nullptr, 1.0, CBAA_THR_THM2,
                      (cbaa_restore_stats*)nullptr);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
   return run_est(d, cube, hosts, n, rs.eps, est, zeros, layer_zeros, s);
+}
+
+int launch_features(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
+                    uint32_t F, float* x, void* scratch, hipStream_t s) {
+  RestoreScratch rs = carve(d, scratch, 0);
+  int rc = run_scan(d, cube, rs.zeros, rs.ones, nullptr, s);
+  if (rc != CBAA_OK) return rc;
+  hipLaunchKernelGGL(k_prepare, dim3(d.S, 1), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
+                     rs.eps, rs.zmax, rs.hcnt, (uint16_t*)nullptr, 1.0, CBAA_THR_THM2,
+                     (cbaa_restore_stats*)nullptr);
+  if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
+  return run_feat(d, cube, hosts, n, rs.eps, F, x, s);
 }
 
 }  // namespace cbaa

@@ -31,10 +31,27 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-def _gpu_cube(cb, p, pairs, side, scratch=None):
+def _update_scratch(cb, p, n, n_cubes, path, small=False):
+    """Scratch for the partitioned path (None selects direct atomics)."""
+    if path == "direct":
+        return None
+    need = cb.cbaa_update_scratch_bytes(p, n, n_cubes)
+    if need == 0:          # configuration outside the partitioned path's limits
+        return None
+    if small:              # force several passes over the batch
+        need = max(need // 3, 1)
+        need = max(need, cb.cbaa_update_scratch_bytes(p, 65536, n_cubes))
+    return cb.scratch_tensor(need)
+
+
+def _gpu_cube(cb, p, pairs, side, path="direct", small=False):
     cube = cb.new_cube(p)
+    scratch = _update_scratch(cb, p, len(pairs), 1, path, small)
     cb.cbaa_update(p, cube, cb.pairs_to_device(pairs), side, scratch)
     return cube
+
+
+PATHS = ["direct", "partitioned"]
 
 
 def _assert_hosts_equal(got, want):
@@ -47,46 +64,53 @@ def _assert_hosts_equal(got, want):
 
 # ---------------------------------------------------------------- update
 
+@pytest.mark.parametrize("path", PATHS)
 @pytest.mark.parametrize("name", sorted(TINY_CONFIGS))
 @pytest.mark.parametrize("side", [0, 1])
-def test_update_tiny_configs_bitexact(cb, name, side):
+def test_update_tiny_configs_bitexact(cb, name, side, path):
     p = TINY_CONFIGS[name]
     t = tiny_trace(100 + side, n_hosts=3000, n_planted=30, fan_in=0.3)
-    _say(name, side, t.n)
-    got = cb.cube_to_numpy(_gpu_cube(cb, p, t.pairs, side))
+    _say(name, side, path, t.n)
+    got = cb.cube_to_numpy(_gpu_cube(cb, p, t.pairs, side, path))
     assert np.array_equal(got, O.cube_of(p, t.pairs, side))
 
 
-def test_update_small_window_bitexact(cb, small_window):
+@pytest.mark.parametrize("path", PATHS)
+def test_update_small_window_bitexact(cb, small_window, path):
     p = default_params()
-    _say("small window", small_window.n)
-    got = cb.cube_to_numpy(_gpu_cube(cb, p, small_window.pairs, 0))
+    _say("small window", path, small_window.n)
+    got = cb.cube_to_numpy(_gpu_cube(cb, p, small_window.pairs, 0, path))
     assert np.array_equal(got, O.cube_of(p, small_window.pairs, 0))
 
 
-def test_update2_both_sides_bitexact(cb):
+@pytest.mark.parametrize("path,small", [("direct", False), ("partitioned", False),
+                                        ("partitioned", True)])
+def test_update2_both_sides_bitexact(cb, path, small):
     import torch
     p = default_params()
     t = tracegen.window_core_edge(12, scale=1 / 16)
-    _say("update2", t.n)
+    _say("update2", path, small, t.n)
     a, b = cb.new_cube(p), cb.new_cube(p)
-    cb.cbaa_update2(p, a, b, cb.pairs_to_device(t.pairs))
+    scratch = _update_scratch(cb, p, t.n, 2, path, small)
+    cb.cbaa_update2(p, a, b, cb.pairs_to_device(t.pairs), scratch)
     torch.cuda.synchronize()
     assert np.array_equal(cb.cube_to_numpy(a), O.cube_of(p, t.pairs, 0))
     assert np.array_equal(cb.cube_to_numpy(b), O.cube_of(p, t.pairs, 1))
 
 
-@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 1000003])
-def test_update_ragged_sizes(cb, n):
+@pytest.mark.parametrize("path", PATHS)
+@pytest.mark.parametrize("n", [0, 1, 63, 64, 65, 65535, 65536, 65537, 1000003])
+def test_update_ragged_sizes(cb, n, path):
     p = default_params()
     rng = np.random.default_rng(n)
     pairs = rng.integers(0, 1 << 32, (n, 2), dtype=np.uint64).astype(np.uint32)
-    _say("ragged", n)
-    got = cb.cube_to_numpy(_gpu_cube(cb, p, pairs, 0))
+    _say("ragged", path, n)
+    got = cb.cube_to_numpy(_gpu_cube(cb, p, pairs, 0, path))
     assert np.array_equal(got, O.cube_of(p, pairs, 0))
 
 
-def test_update_skewed_single_host_and_repeats(cb):
+@pytest.mark.parametrize("path", PATHS)
+def test_update_skewed_single_host_and_repeats(cb, path):
     p = default_params()
     rng = np.random.default_rng(5)
     n = 2_000_000
@@ -94,8 +118,31 @@ def test_update_skewed_single_host_and_repeats(cb):
                          rng.integers(0, 1 << 32, n, dtype=np.uint64).astype(np.uint32)], axis=1)
     same_pair = np.tile(np.array([[1, 2]], np.uint32), (n, 1))
     for pairs in (one_host, same_pair):
-        got = cb.cube_to_numpy(_gpu_cube(cb, p, pairs, 0))
+        _say("skew", path)
+        got = cb.cube_to_numpy(_gpu_cube(cb, p, pairs, 0, path))
         assert np.array_equal(got, O.cube_of(p, pairs, 0))
+
+
+def test_update_partitioned_onto_nonempty_cube(cb):
+    """The partitioned path ORs into what the cube already holds."""
+    import torch
+    p = default_params()
+    t = tracegen.window_core_edge(15, scale=1 / 64)
+    half = t.n // 2
+    cube = _gpu_cube(cb, p, t.pairs[:half], 1, "direct")
+    scratch = _update_scratch(cb, p, t.n - half, 1, "partitioned")
+    cb.cbaa_update(p, cube, cb.pairs_to_device(t.pairs[half:]), 1, scratch)
+    torch.cuda.synchronize()
+    assert np.array_equal(cb.cube_to_numpy(cube), O.cube_of(p, t.pairs, 1))
+
+
+def test_update_scratch_too_small_rejected(cb):
+    p = default_params()
+    tiny = cb.scratch_tensor(1024)
+    cube = cb.new_cube(p)
+    with pytest.raises(cb.CbaaError) as ei:
+        cb.cbaa_update(p, cube, cb.pairs_to_device(np.ones((10, 2), np.uint32)), 0, tiny)
+    assert ei.value.code == cb.CBAA_ESCRATCH
 
 
 def test_update_concurrent_streams_and_batches(cb):
@@ -112,8 +159,11 @@ def test_update_concurrent_streams_and_batches(cb):
     streams = [torch.cuda.Stream() for _ in range(3)]
     dev = [cb.pairs_to_device(q) for q in parts]
     torch.cuda.synchronize()
+    scratch = [_update_scratch(cb, p, max(len(q) for q in parts), 1, "partitioned")
+               for _ in range(3)]
     for i, q in enumerate(dev):
-        cb.cbaa_update(p, cube, q, 0, stream=streams[i % 3])
+        # alternate the two update paths on three streams
+        cb.cbaa_update(p, cube, q, 0, scratch[i % 3] if i % 2 else None, stream=streams[i % 3])
     torch.cuda.synchronize()
     assert np.array_equal(cb.cube_to_numpy(cube), O.cube_of(p, t.pairs, 0))
 
@@ -255,7 +305,8 @@ def test_full_core_edge_window(cb, core_edge):
     t = core_edge
     _say("core-edge full", t.n)
     a, b = cb.new_cube(p), cb.new_cube(p)
-    cb.cbaa_update2(p, a, b, cb.pairs_to_device(t.pairs))
+    scratch = _update_scratch(cb, p, t.n, 2, "partitioned")
+    cb.cbaa_update2(p, a, b, cb.pairs_to_device(t.pairs), scratch)
     torch.cuda.synchronize()
     for side, cube in ((0, a), (1, b)):
         want_cube = O.cube_of(p, t.pairs, side)

@@ -1,0 +1,63 @@
+"""Pins of the learned estimator's CPU oracle (oracle/mlp.py): bfloat16
+rounding against hand-worked values and torch's conversion, the gradient
+against central finite differences, Adam against torch.optim.Adam."""
+
+import numpy as np
+import pytest
+
+from oracle import mlp as M
+
+
+def test_param_count_and_layout():
+    for F in (1, 4, 6, 8):
+        assert M.n_params(F) == 64 * F + 64 + 64 * 64 + 64 + 64 + 1
+        theta = np.arange(M.n_params(F), dtype=np.float64)
+        W1, b1, W2, b2, w3, b3 = M.split(theta, F)
+        assert W1.shape == (64, F) and W2.shape == (64, 64) and b3.shape == (1,)
+        assert M.weight_mask(F).sum() == 64 * F + 64 * 64 + 64
+
+
+def test_bf16_rounding_hand_values():
+    # spacing at 1.0 is 2^-7; exact halves go to the even mantissa
+    vals = np.array([1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -8 + 2 ** -20, -2.5, 0.0],
+                    np.float32)
+    want = np.array([1.0, 1.0, 1 + 2 ** -6, 1 + 2 ** -7, -2.5, 0.0], np.float32)
+    assert np.array_equal(M.to_bf16(vals), want)
+
+
+def test_bf16_rounding_matches_torch():
+    import torch
+    rng = np.random.default_rng(0)
+    x = (rng.standard_normal(100000) * np.exp(rng.uniform(-20, 20, 100000))).astype(np.float32)
+    t = torch.from_numpy(x).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(M.to_bf16(x), t)
+
+
+@pytest.mark.parametrize("F", [4, 6])
+def test_gradient_matches_finite_differences(F):
+    rng = np.random.default_rng(F)
+    theta = rng.standard_normal(M.n_params(F)) * 0.3
+    x = rng.uniform(0, 1, (40, F))
+    t = rng.uniform(0, 8, 40)
+    loss, g = M.loss_and_grad(theta, F, x, t)
+    idx = rng.choice(M.n_params(F), 120, replace=False)
+    fd = M.finite_difference_grad(theta, F, x, t, idx)
+    assert np.allclose(g[idx], fd, rtol=1e-5, atol=1e-8)
+    assert loss > 0
+
+
+def test_adam_matches_torch():
+    import torch
+    rng = np.random.default_rng(3)
+    P = 500
+    w = rng.standard_normal(P)
+    m = np.zeros(P)
+    v = np.zeros(P)
+    p = torch.nn.Parameter(torch.from_numpy(w.copy()))
+    opt = torch.optim.Adam([p], lr=1e-2, betas=(0.9, 0.999), eps=1e-8)
+    for step in range(1, 4):
+        g = rng.standard_normal(P)
+        p.grad = torch.from_numpy(g.copy())
+        opt.step()
+        w, m, v = M.adam_step(w, g, m, v, step, 1e-2)
+        assert np.allclose(w, p.detach().numpy(), rtol=1e-12, atol=1e-12)

@@ -379,6 +379,16 @@ def test_generator_truth_matches_exact_counts():
         assert src[ip] == d
 
 
+def test_construction_truth_is_exact():
+    t = tracegen.window_core_edge(5, scale=1 / 512)
+    for side in (0, 1):
+        h, c = tracegen.construction_truth(t, side)
+        order = np.argsort(h)
+        hs, cs = O.exact_counts(t.pairs, side)
+        assert np.array_equal(h[order], hs)
+        assert np.array_equal(c[order], cs)
+
+
 def test_detection_rates_definitions():
     """Sec. 5.2: FNR = |H minus detected| / |H|, FPR = |detected with fewer than
     theta peers| / |H| (both over |H|), FTR = FNR + FPR."""

@@ -36,7 +36,7 @@ import math
 import numpy as np
 
 __all__ = ["Trace", "make_window", "window_small", "window_core_edge", "split_routers",
-           "bijection32"]
+           "bijection32", "construction_truth"]
 
 _U32 = np.uint64(0xFFFFFFFF)
 
@@ -69,6 +69,7 @@ class Trace:
     planted_side: np.ndarray     # int8 [P]: 0 = fan-out (host is source), 1 = fan-in
     bg_ips: np.ndarray           # uint32 [S]
     bg_deg: np.ndarray           # int64 [S]
+    key: tuple = (0, 1, 1)       # the bijection's key
 
     @property
     def n(self) -> int:
@@ -160,7 +161,39 @@ def make_window(n_packets: int, n_sources: int, n_planted: int, planted_lo: int,
                   zipf_s=zipf_s, fan_in_frac=fan_in_frac)
     return Trace(pairs=np.ascontiguousarray(pairs), seed=seed, params=params,
                  planted_ips=pl_ips, planted_deg=pdeg, planted_side=pside,
-                 bg_ips=bg_ips, bg_deg=bdeg)
+                 bg_ips=bg_ips, bg_deg=bdeg, key=key)
+
+
+def construction_truth(t: Trace, side: int) -> tuple[np.ndarray, np.ndarray]:
+    """Every host of one side with its exact number of distinct peers, as the
+    generator built it (side 0: hosts are sources, 1: destinations).
+
+    Sources: background hosts, fan-out planted hosts, and the peers of fan-in
+    planted hosts (one peer each). Destinations: fan-in planted hosts and the
+    peers of every other flow (one peer each)."""
+    n_bg = t.bg_ips.size
+    deg = np.concatenate([t.bg_deg, t.planted_deg])
+    ends = np.cumsum(deg)
+    starts = ends - deg
+    fan_in = np.concatenate([np.zeros(n_bg, bool), t.planted_side.astype(bool)])
+
+    def peers_of(mask):
+        idx = np.concatenate([np.arange(a, b, dtype=np.uint64)
+                              for a, b in zip(starts[mask], ends[mask])]) \
+            if mask.any() else np.zeros(0, np.uint64)
+        return bijection32(np.uint64(1 << 31) + idx, t.key)
+
+    if side == 0:
+        out_pl = t.planted_side == 0
+        peers = peers_of(fan_in)
+        hosts = np.concatenate([t.bg_ips, t.planted_ips[out_pl], peers])
+        counts = np.concatenate([t.bg_deg, t.planted_deg[out_pl], np.ones(peers.size, np.int64)])
+    else:
+        in_pl = t.planted_side == 1
+        peers = peers_of(~fan_in)
+        hosts = np.concatenate([t.planted_ips[in_pl], peers])
+        counts = np.concatenate([t.planted_deg[in_pl], np.ones(peers.size, np.int64)])
+    return hosts.astype(np.uint32), counts
 
 
 def window_small(seed: int = 1) -> Trace:
