@@ -1,18 +1,27 @@
 """Benchmark of the CBAA hot path on one MI355X.
 
 One step = one window of the core-edge workload through every stage:
-  per edge router: zero its two local cubes, take its packets into both
-  (source-keyed and destination-keyed, one read of each pair);
-  global server: OR-merge the routers' cubes; restore the super hosts of
-  both global cubes; copy the two sorted lists and counters to the host.
+  local servers: zero each edge router's two cubes, take every router's
+  packets into its source-keyed and destination-keyed cubes (one read of
+  each pair; all routers in one batched launch sequence);
+  global server: OR-merge the routers' cubes, restore the super hosts of
+  both global cubes, copy both sorted lists and counters to pinned host
+  memory.
+The step is captured once in a HIP graph and replayed (``--eager`` launches it
+directly instead).
 
 Workload: 64 x 2^20 synthetic packets (8M Zipf(1.1) sources, 1000 planted
-hosts of 1k-200k peers, half fan-out and half fan-in, 10% duplicates),
-split at random over the edge routers; paper dimensions r=4, |RA|=3, |VA|=1,
-g=c=2^12 (128 MiB per cube); theta = 1024. Inputs are resident in HBM
-before timing starts.
+hosts of 1k-200k peers, half fan-out and half fan-in, 10% duplicates), split
+at random over the edge routers; paper dimensions r=4, |RA|=3, |VA|=1,
+g=c=2^12 (128 MiB per cube); theta = 1024. Inputs are resident in HBM before
+timing starts.
 
-Prints one JSON line (rank 0). Only one GPU is used: --gpus above 1 exits.
+Besides the headline throughput the JSON line carries per-phase times, the
+roofline of the update, a serving run (Poisson chunk arrivals from 16
+routers, continuous batching; p50/p99 chunk-to-result latency), the learned
+estimator against linear counting, and the CPU oracle's throughput.
+
+Only one GPU is used: --gpus above 1 exits.
 """
 
 from __future__ import annotations
@@ -40,10 +49,18 @@ def parse():
     ap.add_argument("--seed", type=int, default=11)
     ap.add_argument("--scale", type=float, default=1.0, help="workload scale (1.0 = 64Mi packets)")
     ap.add_argument("--theta", type=float, default=1024.0)
-    ap.add_argument("--update", choices=["auto", "direct", "partitioned"], default="auto")
+    ap.add_argument("--eager", action="store_true", help="launch the step without a HIP graph")
+    ap.add_argument("--tune", action="store_true", help="autotune the update's shapes first")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="packets of the window the CPU oracle step is timed on (0 = all)")
+    ap.add_argument("--workload", choices=["core-edge", "batched"], default="core-edge",
+                    help="batched: 32 router streams of 1M-64M packets in one graph replay")
+    ap.add_argument("--streams", type=int, default=32)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -62,13 +79,17 @@ def main():
     import torch
 
     import tracegen
-    from paper_1901_06207_amd import cbaa
+    from paper_1901_06207_amd import autotune, cbaa
 
     cbaa.lib()
     dev = torch.device("cuda", 0)
     torch.cuda.set_device(dev)
     cfg = cbaa.cbaa_config_default()
     cube_bytes = cbaa.cbaa_cube_bytes(cfg)
+    if args.calibrate_copy:
+        calibrate_copy(dev)
+    if args.workload == "batched":
+        return bench_batched(cfg, dev, args)
 
     t0 = time.time()
     trace = tracegen.window_core_edge(args.seed, scale=args.scale)
@@ -76,19 +97,17 @@ def main():
     log(f"generated {trace.n} packets in {time.time() - t0:.1f}s; routers "
         f"{[len(q) for q in parts]}")
     d_parts = [cbaa.pairs_to_device(q, dev) for q in parts]
+    local = [(cbaa.new_cube(cfg, dev), cbaa.new_cube(cfg, dev)) for _ in parts]
+    table = [(q, a, b, cbaa.SIDE_SRC) for q, (a, b) in zip(d_parts, local)]
+    tuning = None
+    tune_info = None
+    if args.tune:
+        tune_info = autotune.tune_update(cfg, table)
+        tuning = tune_info["best"]
+        log(f"autotuned: {tune_info['best']} {tune_info['best_ms']:.3f} ms "
+            f"(default {tune_info['default_ms']:.3f} ms)")
+    scratch_u = cbaa.scratch_tensor(cbaa.cbaa_update_batch_scratch_bytes(cfg, table, tuning), dev)
 
-    use_part = args.update != "direct"
-    scratch_u = None
-    if use_part:
-        need = max(cbaa.cbaa_update_scratch_bytes(cfg, len(q), 2) for q in parts)
-        if need > 0:
-            scratch_u = cbaa.scratch_tensor(need, dev)
-        elif args.update == "partitioned":
-            raise SystemExit("partitioned update not available for this configuration")
-    update_path = "partitioned" if scratch_u is not None else "direct"
-
-    local = [(cbaa.new_cube(cfg, dev, init=False), cbaa.new_cube(cfg, dev, init=False))
-             for _ in parts]
     g_src = cbaa.new_cube(cfg, dev, init=False)
     g_dst = cbaa.new_cube(cfg, dev, init=False)
     capacity = 1 << 14
@@ -99,88 +118,108 @@ def main():
     h_outs = [torch.empty(capacity * cbaa.HOST_BYTES, dtype=torch.uint8, pin_memory=True)
               for _ in range(2)]
     h_stats = [torch.empty(4, dtype=torch.int64, pin_memory=True) for _ in range(2)]
-    stream = torch.cuda.current_stream(dev)
 
     ev = {}
 
-    def mark(name):
+    def mark(name, stream):
         e = torch.cuda.Event(enable_timing=True)
         e.record(stream)
         ev.setdefault(name, []).append(e)
 
-    def step(timed_phases=False):
-        if timed_phases:
-            mark("update_begin")
-        for (a, b), q in zip(local, d_parts):
+    def step(stream, timed=False):
+        if timed:
+            mark("init", stream)
+        for a, b in local:
             cbaa.cbaa_cube_init(cfg, a, stream)
             cbaa.cbaa_cube_init(cfg, b, stream)
-            if timed_phases:
-                mark("u2_begin")
-            cbaa.cbaa_update2(cfg, a, b, q, scratch_u, stream)
-            if timed_phases:
-                mark("u2_end")
-        if timed_phases:
-            mark("merge_begin")
+        if timed:
+            mark("update", stream)
+        cbaa.cbaa_update_batch(cfg, table, scratch_u, tuning, stream)
+        if timed:
+            mark("merge", stream)
         cbaa.cbaa_merge_or(cfg, g_src, [x[0] for x in local], stream)
         cbaa.cbaa_merge_or(cfg, g_dst, [x[1] for x in local], stream)
-        if timed_phases:
-            mark("restore_begin")
+        if timed:
+            mark("restore", stream)
         for i, cube in enumerate((g_src, g_dst)):
             cbaa.cbaa_restore(cfg, cube, args.theta, cbaa.THR_THM2, scratch_r[i], outs[i], capacity,
                               stats[i], stream)
-            h_stats[i].copy_(stats[i], non_blocking=True)
-            h_outs[i].copy_(outs[i], non_blocking=True)
-        if timed_phases:
-            mark("restore_end")
+        if timed:
+            mark("copy", stream)
+        with torch.cuda.stream(stream):
+            for i in range(2):
+                h_stats[i].copy_(stats[i], non_blocking=True)
+                h_outs[i].copy_(outs[i], non_blocking=True)
+        if timed:
+            mark("end", stream)
 
+    stream = torch.cuda.Stream(device=dev)
     for _ in range(args.warmup):
-        step()
+        step(stream)
     torch.cuda.synchronize(dev)
     n_found = [int(h_stats[i][0]) for i in range(2)]
     if max(n_found) > capacity:
         raise SystemExit(f"restore capacity {capacity} too small for {n_found}")
+    ref_lists = [h_outs[i][: n_found[i] * 16].clone() for i in range(2)]
     log(f"super hosts found: source-keyed {n_found[0]}, destination-keyed {n_found[1]}")
+
+    graph = None
+    if not args.eager:
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            step(stream)
+        torch.cuda.synchronize(dev)
+        for _ in range(args.warmup):
+            graph.replay()
+        torch.cuda.synchronize(dev)
+        for i in range(2):   # the replayed step reproduces the eager lists
+            if int(h_stats[i][0]) != n_found[i] or not torch.equal(
+                    h_outs[i][: n_found[i] * 16], ref_lists[i]):
+                raise SystemExit("graph replay differs from the eager step")
 
     # timed region: exactly K steps
     torch.cuda.synchronize(dev)
     t_start = time.perf_counter()
     for _ in range(args.steps):
-        step()
+        if graph is not None:
+            graph.replay()
+        else:
+            step(stream)
     torch.cuda.synchronize(dev)
     elapsed = time.perf_counter() - t_start
     ms_per_step = elapsed * 1e3 / args.steps
     value = trace.n / (elapsed / args.steps) / 1e9
 
-    # per-phase breakdown with events on the launch stream (separate pass)
+    # per-phase breakdown with events on the launch stream (eager pass)
     ev.clear()
     phase_steps = max(3, min(args.steps, 10))
     for _ in range(phase_steps):
-        step(timed_phases=True)
+        step(stream, timed=True)
     torch.cuda.synchronize(dev)
 
     def span(a, b):
-        return [x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]
+        return np.array([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])])
 
-    upd_ms = np.array(span("u2_begin", "u2_end"))          # one per router per step
-    merge_ms = np.mean(span("merge_begin", "restore_begin"))
-    restore_ms = np.array(span("restore_begin", "restore_end")) / 2.0   # per window (cube)
-    window_update_ms = np.mean(span("update_begin", "merge_begin"))
-    pkts_per_router = np.mean([len(q) for q in parts])
-    upd_gpkts = pkts_per_router / (upd_ms.mean() * 1e-3) / 1e9
+    init_ms = span("init", "update")
+    upd_ms = span("update", "merge")
+    merge_ms = span("merge", "restore")
+    restore_ms = span("restore", "copy") / 2.0   # per window (global cube)
+    copy_ms = span("copy", "end")
+    upd_gpkts = trace.n / (upd_ms.mean() * 1e-3) / 1e9
 
-    # roofline of the dominant kernel set: the update call (algorithmic bytes =
-    # 8 B per packet read + both cubes written once)
-    upd_alg_bytes = 8.0 * pkts_per_router + 2.0 * cube_bytes
+    # roofline of the dominant kernel set, the batched update call: algorithmic
+    # bytes = 8 B per packet read + every router cube written once
+    upd_alg_bytes = 8.0 * trace.n + 2.0 * len(parts) * cube_bytes
     achieved = upd_alg_bytes / (upd_ms.mean() * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": f"cbaa_update2 ({update_path})",
-                "per_launch": {"packets": int(pkts_per_router), "alg_bytes": int(upd_alg_bytes),
+                "kernel": "cbaa_update_batch (histogram, scan, scatter, apply)",
+                "per_launch": {"packets": int(trace.n), "alg_bytes": int(upd_alg_bytes),
                                "avg_ms": round(float(upd_ms.mean()), 4)}}
 
-    cpu = None
-    if not args.no_cpu_baseline:
-        cpu = cpu_baseline(trace.pairs, args.cpu_sample, args.theta)
+    serving = None if args.no_serve else bench_serving(cfg, dev, args)
+    learned = None if args.no_learned else bench_learned(cfg, trace, g_src, local, dev, args)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(trace.pairs, args.cpu_sample, args.theta)
 
     out = {
         "metric": METRIC,
@@ -200,26 +239,253 @@ def main():
                          "hosts 1k-200k peers, 10% duplicates), source- and destination-keyed "
                          f"cubes, {args.routers} edge routers OR-merged, theta {args.theta:g}, "
                          "r=4 |RA|=3 |VA|=1 g=c=4096"),
-            "packets": trace.n, "routers": args.routers, "update_path": update_path,
-            "seed": args.seed,
+            "packets": trace.n, "routers": args.routers, "seed": args.seed,
+            "launch": "eager" if graph is None else "hip-graph",
+            "tuning": tuning or "default",
         },
         "phases": {
+            "cube_init_ms": round(float(init_ms.mean()), 4),
+            "update_ms": round(float(upd_ms.mean()), 4),
             "update_gpkt_s": round(float(upd_gpkts), 3),
-            "update_ms_per_window": round(float(window_update_ms), 4),
-            "merge_ms": round(float(merge_ms), 4),
+            "merge_ms": round(float(merge_ms.mean()), 4),
             "restore_ms_per_window": round(float(restore_ms.mean()), 4),
             "restore_ms_p99": round(float(np.percentile(restore_ms, 99)), 4),
+            "lists_to_host_ms": round(float(copy_ms.mean()), 4),
             "super_hosts": {"source_keyed": n_found[0], "destination_keyed": n_found[1]},
         },
         "roofline": roofline,
+        "serving": serving,
+        "learned": learned,
         "cpu_baseline": cpu,
+    }
+    if tune_info:
+        out["autotune"] = {"best": tune_info["best"], "best_ms": round(tune_info["best_ms"], 4),
+                           "default_ms": round(tune_info["default_ms"], 4)}
+    print(json.dumps(out), flush=True)
+
+
+def calibrate_copy(dev, nbytes=1 << 30):
+    """A plain device-to-device copy of known size: its FETCH_SIZE/WRITE_SIZE
+    counters scale the update's counters to bytes."""
+    import torch
+    src = torch.ones(nbytes // 8, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize(dev)
+    log(f"calibration copy: {nbytes} bytes read and written per copy, 3 copies")
+
+
+def bench_batched(cfg, dev, args):
+    """K edge-router streams with log-uniform 1M-64M packets (core-edge shape,
+    one seed per stream), both cubes per stream, in one graph replay: zero the
+    cubes, one batched update with autotuned shapes, restore every stream's
+    two cubes, OR-merge all streams into the global cubes, restore those."""
+    import numpy as np
+    import torch
+
+    import tracegen
+    from paper_1901_06207_amd import autotune, cbaa
+
+    rng = np.random.default_rng(args.seed)
+    K = args.streams
+    sizes = np.exp(rng.uniform(np.log(1 << 20), np.log(64 << 20), K)).astype(np.int64)
+    t0 = time.time()
+    d_pairs = []
+    for i, n in enumerate(sizes):
+        tr = tracegen.window_core_edge(args.seed * 1000 + i, scale=float(n) / (64 << 20))
+        d_pairs.append(cbaa.pairs_to_device(tr.pairs, dev))
+        del tr
+    total = int(sum(int(q.shape[0]) for q in d_pairs))
+    log(f"generated {K} streams, {total} packets in {time.time() - t0:.0f}s")
+    cubes = [(cbaa.new_cube(cfg, dev), cbaa.new_cube(cfg, dev)) for _ in range(K)]
+    table = [(q, a, b, cbaa.SIDE_SRC) for q, (a, b) in zip(d_pairs, cubes)]
+    tune = autotune.tune_update(cfg, table, repeats=2)
+    tuning = tune["best"]
+    log(f"autotuned {tuning}: {tune['best_ms']:.2f} ms (default {tune['default_ms']:.2f} ms)")
+    scratch = cbaa.scratch_tensor(cbaa.cbaa_update_batch_scratch_bytes(cfg, table, tuning), dev)
+    g = [cbaa.new_cube(cfg, dev, init=False) for _ in range(2)]
+    cap = 1 << 14
+    rs = cbaa.scratch_tensor(cbaa.cbaa_restore_scratch_bytes(cfg, cap), dev)
+    outs = torch.empty((2 * K + 2, cap * cbaa.HOST_BYTES), dtype=torch.uint8, device=dev)
+    stats = torch.zeros((2 * K + 2, 4), dtype=torch.int64, device=dev)
+    ev = {}
+
+    def mark(name, st):
+        e = torch.cuda.Event(enable_timing=True)
+        e.record(st)
+        ev.setdefault(name, []).append(e)
+
+    def window(st, timed=False):
+        if timed:
+            mark("init", st)
+        for a, b in cubes:
+            cbaa.cbaa_cube_init(cfg, a, st)
+            cbaa.cbaa_cube_init(cfg, b, st)
+        if timed:
+            mark("update", st)
+        cbaa.cbaa_update_batch(cfg, table, scratch, tuning, st)
+        if timed:
+            mark("local_restore", st)
+        for i, (a, b) in enumerate(cubes):
+            for j, c in enumerate((a, b)):
+                cbaa.cbaa_restore(cfg, c, args.theta, cbaa.THR_THM2, rs, outs[2 * i + j], cap,
+                                  stats[2 * i + j], st)
+        if timed:
+            mark("merge", st)
+        cbaa.cbaa_merge_or(cfg, g[0], [c[0] for c in cubes], st)
+        cbaa.cbaa_merge_or(cfg, g[1], [c[1] for c in cubes], st)
+        if timed:
+            mark("global_restore", st)
+        for j in range(2):
+            cbaa.cbaa_restore(cfg, g[j], args.theta, cbaa.THR_THM2, rs, outs[2 * K + j], cap,
+                              stats[2 * K + j], st)
+        if timed:
+            mark("end", st)
+
+    st = torch.cuda.Stream(device=dev)
+    window(st)
+    torch.cuda.synchronize(dev)
+    want = stats.clone()
+    graph = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(graph, stream=st):
+        window(st)
+    for _ in range(args.warmup):
+        graph.replay()
+    torch.cuda.synchronize(dev)
+    if not torch.equal(stats, want):
+        raise SystemExit("graph replay differs from the eager window")
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        graph.replay()
+    torch.cuda.synchronize(dev)
+    el = (time.perf_counter() - t_start) / args.steps
+    ev.clear()
+    for _ in range(3):
+        window(st, timed=True)
+    torch.cuda.synchronize(dev)
+
+    def span(a, b):
+        return float(np.mean([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])]))
+
+    upd = span("update", "local_restore")
+    hosts = stats[:, 0].cpu().numpy()
+    alg = 8.0 * total + 2.0 * K * cbaa.cbaa_cube_bytes(cfg)
+    out = {
+        "metric": METRIC, "value": round(total / el / 1e9, 3), "unit": "Gpkt/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(el * 1e3, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u32",
+        "data": "synthetic",
+        "config": {"workload": (f"batched: {K} router streams, log-uniform 1M-64M packets "
+                                f"({total} in all, core-edge shape, seed per stream), both cubes, "
+                                "one HIP-graph replay per window"),
+                   "packets": total, "streams": K, "tuning": tuning,
+                   "stream_packets": [int(x) for x in sizes]},
+        "phases": {"cube_init_ms": round(span("init", "update"), 3),
+                   "update_ms": round(upd, 3), "update_gpkt_s": round(total / upd / 1e6, 3),
+                   "local_restores_ms": round(span("local_restore", "merge"), 3),
+                   "local_restore_ms_per_cube": round(span("local_restore", "merge") / (2 * K), 4),
+                   "merge_ms": round(span("merge", "global_restore"), 3),
+                   "global_restore_ms": round(span("global_restore", "end"), 3),
+                   "super_hosts_global": [int(hosts[2 * K]), int(hosts[2 * K + 1])]},
+        "roofline": {"bound": "hbm", "achieved": round(alg / (upd * 1e-3) / 1e9, 1),
+                     "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / (upd * 1e-3) / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": "cbaa_update_batch (histogram, scan, scatter, apply)"},
+        "autotune": {"best": tuning, "best_ms": round(tune["best_ms"], 3),
+                     "default_ms": round(tune["default_ms"], 3),
+                     "candidates": len(tune["candidates"])},
+        "cpu_baseline": None,
     }
     print(json.dumps(out), flush=True)
 
 
+def bench_serving(cfg, dev, args):
+    """16 edge routers send Poisson-arriving chunks of 64k-4M pairs; a 60 s
+    simulated window is replayed in compressed time; continuous batching
+    with a 1 GiB staging budget."""
+    import numpy as np
+    import torch
+
+    import tracegen
+    from paper_1901_06207_amd import serve
+
+    n_routers, window_s, lo, hi = 16, 60.0, 65536, 4 << 20
+    rate = 0.25                 # chunks per router per simulated second (~240 per window)
+    events = serve.poisson_schedule(n_routers, window_s, lo, hi, rate, seed=args.seed)
+    total = sum(e[2] for e in events)
+    src = tracegen.window_core_edge(args.seed + 1, scale=min(1.0, total / (64 << 20)))
+    pairs = src.pairs
+    chunks, pos = [], 0
+    for _, _, size in events:
+        if pos + size > len(pairs):
+            pos = 0
+        q = np.ascontiguousarray(pairs[pos:pos + size]).view(np.int32)
+        pos += size
+        chunks.append(torch.from_numpy(q).pin_memory())
+    srv = serve.Server(cfg, n_routers, both_sides=True, staging_bytes=1 << 30, device=dev)
+    # warm the kernels once on a few chunks
+    serve.run_window(srv, events[:8], chunks[:8], time_scale=0.0)
+    # saturation: every chunk arrives at once
+    sat = serve.run_window(srv, events, chunks, time_scale=0.0)
+    # offered load: the simulated 60 s window replayed so that packets arrive at
+    # `offered` Gpkt/s on average (Poisson arrivals scaled in time)
+    offered = 2.0
+    time_scale = total / (offered * 1e9) / window_s
+    srv.batches = 0
+    res = serve.run_window(srv, events, chunks, time_scale=time_scale)
+    return {"routers": n_routers, "chunks": res["chunks"], "packets": res["packets"],
+            "chunk_pairs": [lo, hi], "simulated_window_s": window_s,
+            "replay_window_s": round(window_s * time_scale, 4),
+            "saturation_gpkt_s": round(sat["gpkt_s"], 3),
+            "offered_gpkt_s": offered, "gpkt_s": round(res["gpkt_s"], 3),
+            "p50_ms": round(res["p50_ms"], 3), "p99_ms": round(res["p99_ms"], 3),
+            "batches": res["batches"],
+            "staging_peak_mib": round(res["staging_peak_bytes"] / 2 ** 20, 1),
+            "window_restore_ms": round(res["restore_ms"], 3),
+            "note": "chunks are copied host-to-device inside the measured latency"}
+
+
+def bench_learned(cfg, trace, g_src, local, dev, args):
+    """The learned estimator trained on half of the window's source hosts
+    (labels: the generator's construction counts) and compared with the
+    paper's linear count on the other half at equal false-negative rate."""
+    import numpy as np
+    import torch
+
+    import tracegen
+    from paper_1901_06207_amd import cbaa, learned
+
+    # the global source-keyed cube of the last step holds the whole window
+    hosts, counts = tracegen.construction_truth(trace, 0)
+    rng = np.random.default_rng(args.seed)
+    perm = rng.permutation(hosts.size)
+    half = perm.size // 2
+    tr_pool, te = perm[:half], perm[half:]
+    tr = tr_pool[learned.stratified_rows(counts[tr_pool], 100_000, rng)]
+    te = rng.choice(te, min(te.size, 2_000_000), replace=False)
+    t0 = time.perf_counter()
+    x_tr = learned.features(cfg, g_src, hosts[tr])
+    model = learned.Model.new(x_tr.shape[1], seed=1)
+    tl = learned.train(model, x_tr, torch.from_numpy(np.log1p(counts[tr]).astype(np.float32)).to(dev),
+                       epochs=20, batch=16384)
+    torch.cuda.synchronize(dev)
+    train_s = time.perf_counter() - t0
+    x_te = learned.features(cfg, g_src, hosts[te])
+    est_ml = learned.predict(model, x_te).cpu().numpy()
+    est_lc = learned.linear_count(cfg, g_src, hosts[te])
+    rep = learned.compare(est_lc, est_ml, counts[te], args.theta)
+    return {"train_rows": int(tr.size), "test_rows": int(te.size), "epochs": tl.epochs,
+            "train_s": round(train_s, 2), "final_loss": round(tl.final_loss, 5),
+            "lc": {k: round(v, 5) for k, v in rep["lc"].items()},
+            "mlp": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep["mlp"].items()},
+            "bins": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in b.items()}
+                     for b in rep["bins"]]}
+
+
 def cpu_baseline(pairs, sample, theta):
     """The oracle's step (both cubes' update, both restores) on the first
-    `sample` packets of the window, single-threaded on the host."""
+    `sample` packets of the window (all by default), single-threaded."""
     import oracle as O
     p = O.default_params()
     s = pairs[:sample] if sample else pairs
@@ -230,8 +496,8 @@ def cpu_baseline(pairs, sample, theta):
     O.restore(p, b, theta)
     dt = time.perf_counter() - t0
     return {"value": round(len(s) / dt / 1e9, 6), "unit": "Gpkt/s", "cores": 1, "kind": "oracle",
-            "sample": (f"first {len(s)} packets of the window: oracle update of both cubes plus "
-                       f"both restores, {dt:.1f}s single-threaded")}
+            "sample": (f"{len(s)} packets of the window: oracle update of both cubes "
+                       f"plus both restores, {dt:.1f}s single-threaded")}
 
 
 if __name__ == "__main__":

@@ -41,10 +41,11 @@ extern "C" {
 /* Number of parameters for F features (1 <= F <= 8), 0 otherwise. */
 uint32_t cbaa_mlp_param_count(uint32_t n_features);
 
-/* He-uniform weights from a counter-based hash of (seed, index), zero biases;
- * writes the master and its bf16 copy. */
-int cbaa_mlp_init(uint32_t n_features, uint32_t seed, float* d_master, uint16_t* d_wbf,
-                  void* stream);
+/* He-uniform weights from a counter-based hash of (seed, index), zero biases,
+ * and with zero_output != 0 a zero output layer (w3 = 0, b3 = 0: the network
+ * then outputs exactly 0); writes the master and its bf16 copy. */
+int cbaa_mlp_init(uint32_t n_features, uint32_t seed, int zero_output, float* d_master,
+                  uint16_t* d_wbf, void* stream);
 
 /* Per-host features from a cube (see above). n_features is n_ra + n_va or
  * n_ra + n_va + 2. d_scratch holds cbaa_restore_scratch_bytes(cfg, 0). */

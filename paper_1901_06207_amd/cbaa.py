@@ -146,7 +146,7 @@ def lib():
         "cbaa_restore": (i32, [cfgp, vp, dbl, i32, vp, u64, vp, u64, vp, vp]),
         "cbaa_estimate": (i32, [cfgp, vp, vp, u64, vp, vp, vp, vp, u64, vp]),
         "cbaa_mlp_param_count": (C.c_uint32, [C.c_uint32]),
-        "cbaa_mlp_init": (i32, [C.c_uint32, C.c_uint32, vp, vp, vp]),
+        "cbaa_mlp_init": (i32, [C.c_uint32, C.c_uint32, i32, vp, vp, vp]),
         "cbaa_mlp_features": (i32, [cfgp, vp, vp, u64, C.c_uint32, vp, vp, u64, vp]),
         "cbaa_mlp_forward": (i32, [C.c_uint32, vp, vp, vp, u64, vp, vp]),
         "cbaa_mlp_loss_grad": (i32, [C.c_uint32, vp, vp, vp, vp, u64, vp, vp, vp]),
@@ -338,9 +338,9 @@ def cbaa_mlp_param_count(n_features: int) -> int:
 
 
 def cbaa_mlp_init(n_features: int, seed: int, master: torch.Tensor, wbf: torch.Tensor,
-                  stream=None) -> None:
-    _check(lib().cbaa_mlp_init(n_features, seed, _dev_ptr(master, "master"), _dev_ptr(wbf, "wbf"),
-                               _stream(stream)), "cbaa_mlp_init")
+                  zero_output: bool = False, stream=None) -> None:
+    _check(lib().cbaa_mlp_init(n_features, seed, int(zero_output), _dev_ptr(master, "master"),
+                               _dev_ptr(wbf, "wbf"), _stream(stream)), "cbaa_mlp_init")
 
 
 def cbaa_mlp_features(cfg, cube: torch.Tensor, hosts: torch.Tensor, n_features: int,

@@ -278,8 +278,10 @@ __global__ void k_mlp_adam(uint32_t P, float* master, uint16_t* wbf, const float
   wbf[i] = f32_to_bf16(w);
 }
 
-// He-uniform weights from a counter-based hash of (seed, index); zero biases.
-__global__ void k_mlp_init(uint32_t F, uint32_t seed, float* master, uint16_t* wbf) {
+// He-uniform weights from a counter-based hash of (seed, index); zero biases;
+// optionally a zero output layer (the network then outputs exactly 0).
+__global__ void k_mlp_init(uint32_t F, uint32_t seed, int zero_output, float* master,
+                           uint16_t* wbf) {
   const Offsets o = offsets(F);
   const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= o.P) return;
@@ -287,7 +289,7 @@ __global__ void k_mlp_init(uint32_t F, uint32_t seed, float* master, uint16_t* w
   float fan_in = 0.0f;
   if (i < o.b1) fan_in = (float)F;
   else if (i >= o.W2 && i < o.b2) fan_in = (float)kH;
-  else if (i >= o.w3 && i < o.b3) fan_in = (float)kH;
+  else if (i >= o.w3 && i < o.b3 && !zero_output) fan_in = (float)kH;
   if (fan_in > 0.0f) {
     const uint32_t h = lowbias32(fmix32(seed) ^ (i * 0x9E3779B9u));
     const float u = (float)(h >> 8) * (1.0f / 16777216.0f);  // [0, 1)
@@ -321,14 +323,15 @@ uint32_t cbaa_mlp_param_count(uint32_t n_features) {
   return offsets(n_features).P;
 }
 
-int cbaa_mlp_init(uint32_t F, uint32_t seed, float* d_master, uint16_t* d_wbf, void* stream) {
+int cbaa_mlp_init(uint32_t F, uint32_t seed, int zero_output, float* d_master, uint16_t* d_wbf,
+                  void* stream) {
   if (F < 1 || F > kMaxF || !d_master || !d_wbf) {
     set_error("bad feature count or null buffer");
     return CBAA_EINVAL;
   }
   const uint32_t P = offsets(F).P;
   hipLaunchKernelGGL(k_mlp_init, dim3((P + 255) / 256), dim3(256), 0, (hipStream_t)stream, F, seed,
-                     d_master, d_wbf);
+                     zero_output, d_master, d_wbf);
   return check("mlp init launch");
 }
 

@@ -2,9 +2,13 @@
 C ABI of include/cbaa_mlp.h (all arithmetic in the library's HIP kernels;
 torch only holds device buffers).
 
-The network maps a host's per-array column popcounts (plus, with
-``extended=True``, its union column's popcount and its sketch's eps) to
-ln(1 + cardinality). Labels are supplied by the caller.
+The network reads a host's per-array column popcounts in the log domain of
+the linear count, plus its union column's Thm. 2 count and its sketch's
+g*eps (features of cbaa_mlp_features), and outputs a correction in log space
+of the paper's estimate: ln(1 + n_hat) = x_uc + y, where x_uc = ln(1 + Thm. 2
+estimate) is the union-column feature. A network whose output is zero is the
+paper's estimator, which therefore stays both the starting point and the
+fallback. Labels are supplied by the caller.
 """
 
 from __future__ import annotations
@@ -26,12 +30,14 @@ class Model:
 
     @classmethod
     def new(cls, n_features: int, seed: int = 1, device="cuda") -> "Model":
+        """A fresh network for the extended features (n_ra + n_va + 2)."""
         P = cbaa.cbaa_mlp_param_count(n_features)
-        if P == 0:
-            raise ValueError("1 <= n_features <= 8")
+        if P == 0 or n_features < 3:
+            raise ValueError("3 <= n_features <= 8 (extended features)")
         m = cls(n_features, torch.empty(P, dtype=torch.float32, device=device),
                 torch.empty(P, dtype=torch.int16, device=device))
-        cbaa.cbaa_mlp_init(n_features, seed, m.master, m.wbf)
+        # zero output layer: an untrained network is exactly the linear count
+        cbaa.cbaa_mlp_init(n_features, seed, m.master, m.wbf, zero_output=True)
         return m
 
     def state(self) -> dict:
@@ -51,10 +57,16 @@ def features(cfg, cube: torch.Tensor, hosts: np.ndarray, extended: bool = True) 
     return x[:n]
 
 
+def base_log(x: torch.Tensor) -> torch.Tensor:
+    """ln(1 + Thm. 2 estimate): the union-column feature (second to last)."""
+    return x[:, -2]
+
+
 def predict_log(model: Model, x: torch.Tensor) -> torch.Tensor:
+    """ln(1 + n_hat): the linear count's log plus the network's correction."""
     y = torch.empty(x.shape[0], dtype=torch.float32, device=x.device)
     cbaa.cbaa_mlp_forward(model.n_features, model.master, model.wbf, x.contiguous(), y)
-    return y
+    return base_log(x) + y
 
 
 def predict(model: Model, x: torch.Tensor) -> torch.Tensor:
@@ -72,9 +84,11 @@ class TrainLog:
 
 def train(model: Model, x: torch.Tensor, target_log: torch.Tensor, epochs: int = 20,
           batch: int = 65536, lr: float = 2e-3, lr_final: float = 1e-4, seed: int = 0) -> TrainLog:
-    """Adam on mean (y - t)^2 / 2 with a cosine learning-rate decay; minibatches
-    drawn by a seeded permutation each epoch."""
+    """Adam on mean (y - (t - x_uc))^2 / 2, i.e. the log-space error of the
+    corrected estimate, with a cosine learning-rate decay; minibatches drawn
+    by a seeded permutation each epoch. target_log = ln(1 + n)."""
     dev = x.device
+    target_log = (target_log - base_log(x)).contiguous()
     n = x.shape[0]
     P = model.master.numel()
     grad = torch.empty(P, dtype=torch.float32, device=dev)
@@ -101,6 +115,17 @@ def train(model: Model, x: torch.Tensor, target_log: torch.Tensor, epochs: int =
             ep_loss += loss * (xb.shape[0] / n)
         losses.append(float(ep_loss.item()))
     return TrainLog(steps=step, epochs=epochs, final_loss=losses[-1], losses=losses)
+
+
+def stratified_rows(counts: np.ndarray, per_bin: int, rng: np.random.Generator) -> np.ndarray:
+    """Indices of up to per_bin hosts from every power-of-two cardinality bin,
+    so training is not dominated by the many single-peer hosts."""
+    b = np.floor(np.log2(np.maximum(counts, 1))).astype(np.int64)
+    out = []
+    for v in np.unique(b):
+        idx = np.flatnonzero(b == v)
+        out.append(idx if idx.size <= per_bin else rng.choice(idx, per_bin, replace=False))
+    return rng.permutation(np.concatenate(out))
 
 
 def linear_count(cfg, cube: torch.Tensor, hosts: np.ndarray) -> np.ndarray:

@@ -33,8 +33,14 @@ def cb():
 
 
 def _model(cb, F, seed):
+    """A network with every layer random (the output layer too)."""
+    import torch
     from paper_1901_06207_amd import learned
-    return learned.Model.new(F, seed)
+    P = cb.cbaa_mlp_param_count(F)
+    m = learned.Model(F, torch.empty(P, dtype=torch.float32, device="cuda"),
+                      torch.empty(P, dtype=torch.int16, device="cuda"))
+    cb.cbaa_mlp_init(F, seed, m.master, m.wbf)
+    return m
 
 
 def _np(t):
@@ -55,6 +61,14 @@ def test_init_and_bf16_copy(cb, F):
     assert np.all(np.abs(master[mask][: 64 * F]) <= np.sqrt(6 / F))
     assert np.array_equal(wbf[mask], M.to_bf16(master[mask]))
     assert np.std(master[mask][: 64 * F]) > 0.1
+
+
+def test_zero_output_init_is_the_linear_count(cb):
+    import torch
+    from paper_1901_06207_amd import learned
+    m = learned.Model.new(6, seed=5)
+    x = torch.rand(1000, 6, device="cuda") * 8
+    assert torch.equal(learned.predict_log(m, x), learned.base_log(x))
 
 
 @pytest.mark.parametrize("F,n", [(4, 1), (4, 1000), (6, 4097), (8, 200003)])
@@ -130,20 +144,21 @@ def test_features_match_oracle(cb):
     assert np.allclose(x, want, rtol=2e-6, atol=1e-6)
 
 
-def _window_rows(cb, learned, p, seed, scale, side, n_keep, rng):
-    """Features and construction truth for hosts of one window and side,
-    stratified so large cardinalities are not drowned by single-peer hosts."""
+def _window_rows(cb, learned, p, seed, scale, side, per_bin, rng):
+    """Features and construction truth for hosts of one window and side, up to
+    per_bin hosts from each power-of-two cardinality bin (per_bin None: a
+    uniform sample of 1M hosts, the natural mix)."""
     import torch
+    print(f"[case] learned window seed={seed} scale={scale} side={side}", flush=True)
     t = tracegen.window_core_edge(seed, scale=scale)
     a, b = cb.new_cube(p), cb.new_cube(p)
     cb.cbaa_update2(p, a, b, cb.pairs_to_device(t.pairs))
     cube = a if side == 0 else b
     hosts, counts = tracegen.construction_truth(t, side)
-    big = counts >= 16
-    small_idx = np.flatnonzero(~big)
-    n_small = min(small_idx.size, max(int(big.sum()), n_keep - int(big.sum())))
-    take_small = rng.choice(small_idx, n_small, replace=False)
-    sel = np.concatenate([np.flatnonzero(big), take_small])
+    if per_bin is None:
+        sel = rng.choice(hosts.size, min(hosts.size, 1_000_000), replace=False)
+    else:
+        sel = learned.stratified_rows(counts, per_bin, rng)
     x = learned.features(p, cube, hosts[sel], extended=True)
     torch.cuda.synchronize()
     return cube, hosts[sel], counts[sel], x
@@ -160,15 +175,15 @@ def test_trained_network_against_linear_count(cb):
     p = default_params()
     rng = np.random.default_rng(0)
     xs, ts = [], []
-    for seed, side in ((21, 0), (21, 1), (22, 0), (22, 1)):
-        _, _, c, x = _window_rows(cb, learned, p, seed, 0.5, side, 1_000_000, rng)
+    for seed, side in ((21, 0), (21, 1), (22, 0), (22, 1), (24, 0), (25, 0)):
+        _, _, c, x = _window_rows(cb, learned, p, seed, 0.5, side, 100_000, rng)
         xs.append(x)
         ts.append(torch.from_numpy(np.log1p(c).astype(np.float32)).cuda())
     X = torch.cat(xs)
     T = torch.cat(ts)
     model = learned.Model.new(6, seed=3)
-    log = learned.train(model, X, T, epochs=12, batch=32768)
-    cube, hosts, counts, xe = _window_rows(cb, learned, p, 23, 0.5, 0, 1_000_000, rng)
+    log = learned.train(model, X, T, epochs=20, batch=16384)
+    cube, hosts, counts, xe = _window_rows(cb, learned, p, 23, 0.5, 0, None, rng)
     est_ml = learned.predict(model, xe).cpu().numpy()
     est_lc = learned.linear_count(p, cube, hosts)
     rep = learned.compare(est_lc, est_ml, counts, 1024.0)
