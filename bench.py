@@ -27,6 +27,7 @@ Only one GPU is used: --gpus above 1 exits.
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -37,6 +38,26 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# HBM bytes of one update call on the default workload (2 routers, default
+# tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
+# valid only while the update kernels' sources are the ones measured
+# (profiles/update_core_edge_64M_traffic.txt).
+UPDATE_TRAFFIC = {"bytes": 4254335128, "sources": {
+    "paper_1901_06207_amd/csrc/cbaa_partition.hip":
+        "8f6f8847906cfe8e8e683276af87913f35d81167200cb82f03a458a710a86cc7",
+    "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
+        "c679e14ca8c8dc96cf291fc8f2fbdea98f4db76dd8bf9cc460dfc2ed2144d551"}}
+
+
+def measured_traffic(record, default_workload):
+    """The recorded counter bytes if the measured sources are unchanged."""
+    if not default_workload:
+        return None
+    for rel, digest in record["sources"].items():
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != digest:
+                return None
+    return record["bytes"]
 METRIC = "Gpkt/s cube update, ms/window restore, p99 latency; learned vs linear-count err"
 
 
@@ -212,7 +233,9 @@ def main():
     upd_alg_bytes = 8.0 * trace.n + 2.0 * len(parts) * cube_bytes
     achieved = upd_alg_bytes / (upd_ms.mean() * 1e-3) / 1e9
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
-                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": measured_traffic(UPDATE_TRAFFIC, len(parts) == 2 and tuning is None
+                                            and args.scale == 1.0),
                 "kernel": "cbaa_update_batch (histogram, scan, scatter, apply)",
                 "per_launch": {"packets": int(trace.n), "alg_bytes": int(upd_alg_bytes),
                                "avg_ms": round(float(upd_ms.mean()), 4)}}
