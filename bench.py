@@ -1,9 +1,10 @@
 """Benchmark of the CBAA hot path on one MI355X.
 
 One step = one window of the core-edge workload through every stage:
-  local servers: zero each edge router's two cubes, take every router's
-  packets into its source-keyed and destination-keyed cubes (one read of
-  each pair; all routers in one batched launch sequence);
+  local servers: take every router's packets into its source-keyed and
+  destination-keyed cubes, which start the window empty (one read of each
+  pair; all routers in one batched launch sequence flagged fresh, so the
+  update stores whole row blocks instead of zeroing the cubes first);
   global server: OR-merge the routers' cubes, restore the super hosts of
   both global cubes, copy both sorted lists and counters to pinned host
   memory.
@@ -119,7 +120,7 @@ def main():
         f"{[len(q) for q in parts]}")
     d_parts = [cbaa.pairs_to_device(q, dev) for q in parts]
     local = [(cbaa.new_cube(cfg, dev), cbaa.new_cube(cfg, dev)) for _ in parts]
-    table = [(q, a, b, cbaa.SIDE_SRC) for q, (a, b) in zip(d_parts, local)]
+    table = [(q, a, b, cbaa.SIDE_SRC, cbaa.BATCH_FRESH) for q, (a, b) in zip(d_parts, local)]
     tuning = None
     tune_info = None
     if args.tune:
@@ -148,11 +149,6 @@ def main():
         ev.setdefault(name, []).append(e)
 
     def step(stream, timed=False):
-        if timed:
-            mark("init", stream)
-        for a, b in local:
-            cbaa.cbaa_cube_init(cfg, a, stream)
-            cbaa.cbaa_cube_init(cfg, b, stream)
         if timed:
             mark("update", stream)
         cbaa.cbaa_update_batch(cfg, table, scratch_u, tuning, stream)
@@ -221,7 +217,6 @@ def main():
     def span(a, b):
         return np.array([x.elapsed_time(y) for x, y in zip(ev[a], ev[b])])
 
-    init_ms = span("init", "update")
     upd_ms = span("update", "merge")
     merge_ms = span("merge", "restore")
     restore_ms = span("restore", "copy") / 2.0   # per window (global cube)
@@ -267,7 +262,6 @@ def main():
             "tuning": tuning or "default",
         },
         "phases": {
-            "cube_init_ms": round(float(init_ms.mean()), 4),
             "update_ms": round(float(upd_ms.mean()), 4),
             "update_gpkt_s": round(float(upd_gpkts), 3),
             "merge_ms": round(float(merge_ms.mean()), 4),
@@ -322,7 +316,7 @@ def bench_batched(cfg, dev, args):
     total = int(sum(int(q.shape[0]) for q in d_pairs))
     log(f"generated {K} streams, {total} packets in {time.time() - t0:.0f}s")
     cubes = [(cbaa.new_cube(cfg, dev), cbaa.new_cube(cfg, dev)) for _ in range(K)]
-    table = [(q, a, b, cbaa.SIDE_SRC) for q, (a, b) in zip(d_pairs, cubes)]
+    table = [(q, a, b, cbaa.SIDE_SRC, cbaa.BATCH_FRESH) for q, (a, b) in zip(d_pairs, cubes)]
     tune = autotune.tune_update(cfg, table, repeats=2)
     tuning = tune["best"]
     log(f"autotuned {tuning}: {tune['best_ms']:.2f} ms (default {tune['default_ms']:.2f} ms)")
@@ -340,11 +334,6 @@ def bench_batched(cfg, dev, args):
         ev.setdefault(name, []).append(e)
 
     def window(st, timed=False):
-        if timed:
-            mark("init", st)
-        for a, b in cubes:
-            cbaa.cbaa_cube_init(cfg, a, st)
-            cbaa.cbaa_cube_init(cfg, b, st)
         if timed:
             mark("update", st)
         cbaa.cbaa_update_batch(cfg, table, scratch, tuning, st)
@@ -404,8 +393,7 @@ def bench_batched(cfg, dev, args):
                                 "one HIP-graph replay per window"),
                    "packets": total, "streams": K, "tuning": tuning,
                    "stream_packets": [int(x) for x in sizes]},
-        "phases": {"cube_init_ms": round(span("init", "update"), 3),
-                   "update_ms": round(upd, 3), "update_gpkt_s": round(total / upd / 1e6, 3),
+        "phases": {"update_ms": round(upd, 3), "update_gpkt_s": round(total / upd / 1e6, 3),
                    "local_restores_ms": round(span("local_restore", "merge"), 3),
                    "local_restore_ms_per_cube": round(span("local_restore", "merge") / (2 * K), 4),
                    "merge_ms": round(span("merge", "global_restore"), 3),

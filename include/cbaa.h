@@ -176,8 +176,15 @@ typedef struct cbaa_stream_batch {
   void* d_cube;             /* keyed by `side`; keyed by source when d_cube_dst is set */
   void* d_cube_dst;         /* NULL, or the destination-keyed cube (both sides per read) */
   int side;                 /* CBAA_SIDE_*; ignored when d_cube_dst is set */
-  int reserved;
+  int flags;                /* 0 or CBAA_BATCH_FRESH */
 } cbaa_stream_batch;
+
+/* The stream's cube(s) start this call empty: whatever they held before is
+ * overwritten, as if zeroed first (Alg. 1 starts every window from empty
+ * arrays; folding that into the update saves a pass over the cube and lets
+ * the update store whole row blocks instead of OR-ing them). A fresh
+ * stream's cubes may not be named by any other stream of the batch. */
+#define CBAA_BATCH_FRESH 1
 
 /* Tile and partition shapes of the partitioned update (0 = library default):
  * chunk_pairs  pairs per histogram/scatter block (multiple of 1024, <= 2^22)
@@ -197,8 +204,9 @@ uint64_t cbaa_update_batch_scratch_bytes(const cbaa_config* h_cfg,
 
 /* Alg. 1 for the batches of k (1..CBAA_MAX_BATCH) edge routers at once, with
  * uneven sizes, through one sequence of launches of the partitioned path:
- * the same result as k cbaa_update (or cbaa_update2) calls. Either every
- * stream sets d_cube_dst or none does. Streams may share cubes. The scratch
+ * the same result as k cbaa_update (or cbaa_update2) calls (after zeroing
+ * the cubes of streams flagged CBAA_BATCH_FRESH). Either every stream sets
+ * d_cube_dst or none does. Streams without the flag may share cubes. The scratch
  * must hold the whole batch (CBAA_ESCRATCH otherwise); each stream's records
  * (pairs x cubes) must stay below 2^32. Only enqueues device work, so the
  * call can be captured into a HIP graph and replayed. Configurations outside

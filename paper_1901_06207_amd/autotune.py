@@ -24,7 +24,9 @@ _cache: dict = {}
 def _key(cfg, streams):
     c = cfg if isinstance(cfg, cbaa.Config) else cbaa.Config.from_dict(cfg)
     total = sum(int(s[0].shape[0]) for s in streams)
-    return (c, len(streams), streams[0][2] is not None, 1 << max(0, math.ceil(math.log2(max(total, 1)))))
+    fresh = any(len(s) > 4 and s[4] for s in streams)
+    return (c, len(streams), streams[0][2] is not None, fresh,
+            1 << max(0, math.ceil(math.log2(max(total, 1)))))
 
 
 def _time(cfg, streams, tuning, scratch, repeats, stream):

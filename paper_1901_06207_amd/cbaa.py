@@ -50,7 +50,7 @@ class cbaa_restore_stats(C.Structure):
 
 class cbaa_stream_batch(C.Structure):
     _fields_ = [("d_pairs", C.c_void_p), ("n_pairs", C.c_uint64), ("d_cube", C.c_void_p),
-                ("d_cube_dst", C.c_void_p), ("side", C.c_int), ("reserved", C.c_int)]
+                ("d_cube_dst", C.c_void_p), ("side", C.c_int), ("flags", C.c_int)]
 
 
 class cbaa_tuning(C.Structure):
@@ -258,10 +258,15 @@ def cbaa_update2(cfg, cube_src: torch.Tensor, cube_dst: torch.Tensor, pairs: tor
                               sb, _stream(stream)), "cbaa_update2")
 
 
+BATCH_FRESH = 1
+
+
 def _stream_table(streams):
-    """streams: sequence of (pairs, cube, cube_dst or None, side)."""
+    """streams: sequence of (pairs, cube, cube_dst or None, side[, flags])."""
     arr = (cbaa_stream_batch * len(streams))()
-    for i, (pairs, cube, cube_dst, side) in enumerate(streams):
+    for i, entry in enumerate(streams):
+        pairs, cube, cube_dst, side = entry[:4]
+        arr[i].flags = entry[4] if len(entry) > 4 else 0
         p, n = _pairs_ptr(pairs)
         arr[i].d_pairs = p
         arr[i].n_pairs = n

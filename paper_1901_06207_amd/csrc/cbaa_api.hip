@@ -210,6 +210,16 @@ static int check_streams(const Dims& d, const cbaa_stream_batch* h, int k, Strea
     REQUIRE(s.n_pairs == 0 || (s.d_pairs && ((uintptr_t)s.d_pairs & 7u) == 0),
             "stream %d: pairs null or misaligned", i);
     REQUIRE((uint64_t)nc * s.n_pairs < 0xFFFFFFFFull, "stream %d: too many records", i);
+    REQUIRE((s.flags & ~CBAA_BATCH_FRESH) == 0, "stream %d: unknown flags", i);
+    if (s.flags & CBAA_BATCH_FRESH)
+      for (int j = 0; j < k; ++j) {
+        if (j == i) continue;
+        const void* mine[2] = {s.d_cube, s.d_cube_dst};
+        for (const void* c : mine)
+          REQUIRE(!c || (c != h[j].d_cube && c != h[j].d_cube_dst),
+                  "stream %d: a fresh stream's cube is also named by stream %d", i, j);
+      }
+    out[i].fresh = (s.flags & CBAA_BATCH_FRESH) ? 1 : 0;
     out[i].pairs = s.d_pairs;
     out[i].n = s.n_pairs;
     out[i].cube0 = (uint64_t*)s.d_cube;

@@ -108,6 +108,7 @@ struct StreamSpec {
   uint64_t* cube0;
   uint64_t* cube1;
   int side;
+  int fresh;  // cubes start empty (CBAA_BATCH_FRESH)
 };
 
 // ---- host-side helpers (cbaa_api.hip) ----------------------------------

@@ -20,7 +20,11 @@
 //                  contiguously at the bin's cursor
 //   7. apply       persistent blocks walk (stream, bin, segment) items: zero
 //                  an LDS tile, OR the records' bits into it, flush non-zero
-//                  words to the stream's cube
+//                  words to the stream's cube with atomic ORs -- or, for a
+//                  stream whose cubes start empty and a bin with one item,
+//                  store the whole tile (the row block needs no zeroing)
+// Fresh streams' row blocks that no single item owns (empty bins and bins
+// split over several items) are zeroed between steps 5 and 6.
 // A record is the mangled inner IP and the outer IP's bit with the cube index
 // in bit 31 (uint2); the apply step recomputes the columns from the mangled IP.
 #include "cbaa_internal.hpp"
@@ -51,7 +55,7 @@ struct StreamDesc {
   uint32_t chunk_begin;   // first global chunk
   uint32_t group_begin;   // first global group
   uint32_t side;
-  uint32_t pad;
+  uint32_t fresh;         // cubes start empty: row blocks are stored, not OR-ed
 };
 
 struct Batch {
@@ -375,6 +379,23 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b,
   }
 }
 
+// Row blocks of fresh streams that the apply does not store whole: bins with
+// no records (no item) or with several items (OR-ed by each). Block (bin,
+// stream).
+__global__ __launch_bounds__(256) void k_clear_fresh(Dims d, Batch b,
+                                                     const uint32_t* __restrict__ segpre) {
+  const uint32_t bin = blockIdx.x, si = blockIdx.y;
+  const StreamDesc& st = b.s[si];
+  if (!st.fresh) return;
+  const uint32_t* sp = segpre + (uint64_t)si * (b.nbins + 1);
+  if (sp[bin + 1] - sp[bin] == 1) return;
+  const uint32_t per_cube = d.S * d.R;
+  uint64_t* cube = bin < per_cube ? st.cube0 : st.cube1;
+  const uint32_t row = bin < per_cube ? bin : bin - per_cube;
+  uint4* dst = (uint4*)(cube + (uint64_t)row * d.W);   // W is even, cubes 16-byte aligned
+  for (uint32_t w = threadIdx.x; w < d.W / 2; w += 256) dst[w] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 // Largest x in [0, n) with tab[x] <= v (tab ascending, tab[0] <= v < tab[n]).
 __device__ inline uint32_t upper_index(const uint32_t* tab, uint32_t n, uint32_t v) {
   uint32_t lo = 0, hi = n;
@@ -390,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* 
                                                   const uint32_t* __restrict__ base,
                                                   const uint32_t* __restrict__ segpre,
                                                   const uint32_t* __restrict__ items) {
-  __shared__ uint64_t tile[kMaxTileWords];
+  __shared__ __align__(16) uint64_t tile[kMaxTileWords];
   uint32_t* tile32 = (uint32_t*)tile;
   const uint32_t n_items = items[b.k];
   const uint32_t per_cube = d.S * d.R;
@@ -437,9 +458,16 @@ __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* 
     uint64_t* cube = bin < per_cube ? st.cube0 : st.cube1;
     const uint32_t row = bin < per_cube ? bin : bin - per_cube;  // = cs * R + rb
     uint64_t* dst = cube + (uint64_t)row * d.W;
-    for (uint32_t w = threadIdx.x; w < d.W; w += kBlock) {
-      const uint64_t v = tile[w];
-      if (v) __hip_atomic_fetch_or(dst + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (st.fresh && sp[bin + 1] - sp[bin] == 1) {
+      // sole writer of an empty row block: store it whole
+      const uint4* t4 = (const uint4*)tile;
+      uint4* d4 = (uint4*)dst;
+      for (uint32_t w = threadIdx.x; w < d.W / 2; w += kBlock) d4[w] = t4[w];
+    } else {
+      for (uint32_t w = threadIdx.x; w < d.W; w += kBlock) {
+        const uint64_t v = tile[w];
+        if (v) __hip_atomic_fetch_or(dst + w, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+      }
     }
     __syncthreads();
   }
@@ -470,7 +498,16 @@ int run_apply(const Dims& d, const Batch& b, const Layout& L, uint32_t blocks, h
 template <bool TWO>
 int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStream_t s) {
   int rc;
-  if (b.total_chunks == 0) return CBAA_OK;
+  bool any_fresh = false;
+  for (uint32_t i = 0; i < b.k; ++i) any_fresh = any_fresh || b.s[i].fresh;
+  if (b.total_chunks == 0) {   // no pairs at all: fresh cubes are just emptied
+    for (uint32_t i = 0; i < b.k && any_fresh; ++i) {
+      if (!b.s[i].fresh) continue;
+      if ((rc = launch_fill_zero(b.s[i].cube0, d.words, s)) != CBAA_OK) return rc;
+      if (TWO && (rc = launch_fill_zero(b.s[i].cube1, d.words, s)) != CBAA_OK) return rc;
+    }
+    return CBAA_OK;
+  }
   hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.counts);
   if ((rc = check("histogram launch")) != CBAA_OK) return rc;
   const dim3 sgrid((b.nbins + 255) / 256, b.total_groups);
@@ -482,6 +519,10 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
   if ((rc = check("items launch")) != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_offsets, sgrid, dim3(256), 0, s, b, L.counts, L.gsum, L.base);
   if ((rc = check("offsets launch")) != CBAA_OK) return rc;
+  if (any_fresh) {
+    hipLaunchKernelGGL(k_clear_fresh, dim3(b.nbins, b.k), dim3(256), 0, s, d, b, L.segpre);
+    if ((rc = check("clear launch")) != CBAA_OK) return rc;
+  }
   hipLaunchKernelGGL((k_scatter<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.counts,
                      L.rec);
   if ((rc = check("scatter launch")) != CBAA_OK) return rc;
@@ -522,7 +563,7 @@ int launch_update_batch(const Dims& d, const StreamSpec* specs, int k, int n_cub
     b.s[i].cube0 = specs[i].cube0;
     b.s[i].cube1 = specs[i].cube1;
     b.s[i].side = (uint32_t)specs[i].side;
-    b.s[i].pad = 0;
+    b.s[i].fresh = specs[i].fresh ? 1u : 0u;
   }
   const Layout L = plan(d, n_cubes, tu.chunk, b, scratch);
   return n_cubes == 2 ? run<true>(d, b, L, tu.apply_blocks, s)

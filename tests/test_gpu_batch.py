@@ -82,10 +82,66 @@ def test_batch_tunings_and_shared_cube(cb, tuning):
     assert np.array_equal(cb.cube_to_numpy(own), O.cube_of(p, parts[1], 1))
 
 
+def _skewed(seed, n):
+    """n pairs from distinct sources to one destination: in the source-keyed
+    cube every record lands in the row block of that destination's bit, so a
+    few bins hold n / 2^r records each (several apply items per bin)."""
+    rng = np.random.default_rng(seed)
+    src = rng.choice(1 << 32, n, replace=False).astype(np.uint32)
+    return np.stack([src, np.full(n, 0x0A000001, np.uint32)], axis=1)
+
+
+@pytest.mark.parametrize("two", [False, True])
+@pytest.mark.parametrize("tuning", [None, dict(chunk_pairs=4096, seg_records=2048)])
+def test_fresh_streams_overwrite_their_cubes(cb, two, tuning):
+    """Streams flagged fresh start from empty cubes whatever the cubes held
+    (all-ones here): stale bits vanish, an empty stream leaves an empty cube,
+    bins split over several apply items are cleared before they are OR-ed,
+    and a stream without the flag in the same batch still ORs into its cube."""
+    import torch
+    p = default_params()
+    parts = _streams(31 + two, [70_000, 0, 300_000, 4_099]) + [_skewed(5, 120_000)]
+    table, cubes, fresh = [], [], []
+    for i, q in enumerate(parts):
+        a = cb.new_cube(p, init=False)
+        b = cb.new_cube(p, init=False) if two else None
+        is_fresh = i != 3                      # stream 3 keeps the OR semantics
+        for c in (a, b):
+            if c is None:
+                continue
+            if is_fresh:
+                c.fill_(-1)                    # stale content to be overwritten
+            else:
+                cb.cbaa_cube_init(p, c)
+        cubes.append((a, b))
+        fresh.append(is_fresh)
+        dq = cb.pairs_to_device(q) if len(q) else torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+        table.append((dq, a, b, 0, cb.BATCH_FRESH if is_fresh else 0))
+    scratch = cb.scratch_tensor(cb.cbaa_update_batch_scratch_bytes(p, table, tuning))
+    cb.cbaa_update_batch(p, table, scratch, tuning)
+    torch.cuda.synchronize()
+    for i, (q, (a, b)) in enumerate(zip(parts, cubes)):
+        assert np.array_equal(cb.cube_to_numpy(a), O.cube_of(p, q, 0)), (i, fresh[i])
+        if two:
+            assert np.array_equal(cb.cube_to_numpy(b), O.cube_of(p, q, 1)), (i, fresh[i])
+
+
+def test_fresh_batch_without_pairs_empties_cubes(cb):
+    import torch
+    p = default_params()
+    a = cb.new_cube(p, init=False)
+    a.fill_(-1)
+    empty = torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+    table = [(empty, a, None, 0, cb.BATCH_FRESH)]
+    cb.cbaa_update_batch(p, table, cb.scratch_tensor(cb.cbaa_update_batch_scratch_bytes(p, table)))
+    torch.cuda.synchronize()
+    assert not cb.cube_to_numpy(a).any()
+
+
 def test_batch_rejects_bad_tables(cb):
     import torch
     p = default_params()
-    a, b = cb.new_cube(p), cb.new_cube(p)
+    a, b, c = cb.new_cube(p), cb.new_cube(p), cb.new_cube(p)
     pr = cb.pairs_to_device(np.ones((10, 2), np.uint32))
     scratch = cb.scratch_tensor(1 << 20)
     with pytest.raises(cb.CbaaError):          # mixed one- and two-cube streams
@@ -96,20 +152,28 @@ def test_batch_rejects_bad_tables(cb):
         cb.cbaa_update_batch(p, [(pr, a, None, 0)], cb.scratch_tensor(256))
     with pytest.raises(cb.CbaaError):          # tuning out of range
         cb.cbaa_update_batch(p, [(pr, a, None, 0)], scratch, dict(chunk_pairs=1000))
+    with pytest.raises(cb.CbaaError):          # a fresh stream's cube named twice
+        cb.cbaa_update_batch(p, [(pr, a, None, 0, cb.BATCH_FRESH), (pr, a, None, 1)], scratch)
+    with pytest.raises(cb.CbaaError):          # ... also as another stream's second cube
+        cb.cbaa_update_batch(p, [(pr, a, b, 0, cb.BATCH_FRESH), (pr, b, c, 0)], scratch)
+    with pytest.raises(cb.CbaaError):          # unknown flag bits
+        cb.cbaa_update_batch(p, [(pr, a, None, 0, 2)], scratch)
     torch.cuda.synchronize()
 
 
-def test_graph_capture_replays_batch_merge_restore(cb):
-    """The per-window sequence -- zero the routers' cubes, batched update,
-    OR-merge into the global cube, restore -- captured once in a HIP graph and
-    replayed; every replay equals the eager run and the oracle."""
+@pytest.mark.parametrize("fresh", [False, True])
+def test_graph_capture_replays_batch_merge_restore(cb, fresh):
+    """The per-window sequence -- zero the routers' cubes (or flag them fresh),
+    batched update, OR-merge into the global cube, restore -- captured once in
+    a HIP graph and replayed; every replay equals the eager run and the
+    oracle."""
     import torch
     p = default_params()
     parts = _streams(17, [400_000, 900_000, 50_000, 250_000])
     cubes = [cb.new_cube(p) for _ in parts]
     glob = cb.new_cube(p, init=False)
     d_parts = [cb.pairs_to_device(q) for q in parts]
-    table = [(q, c, None, 0) for q, c in zip(d_parts, cubes)]
+    table = [(q, c, None, 0, cb.BATCH_FRESH if fresh else 0) for q, c in zip(d_parts, cubes)]
     scratch = cb.scratch_tensor(cb.cbaa_update_batch_scratch_bytes(p, table))
     cap = 4096
     rs = cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, cap))
@@ -117,8 +181,9 @@ def test_graph_capture_replays_batch_merge_restore(cb):
     st = cb.stats_tensor()
 
     def window():
-        for c in cubes:
-            cb.cbaa_cube_init(p, c)
+        if not fresh:
+            for c in cubes:
+                cb.cbaa_cube_init(p, c)
         cb.cbaa_update_batch(p, table, scratch)
         cb.cbaa_merge_or(p, glob, cubes)
         cb.cbaa_restore(p, glob, 64.0, cb.THR_THM2, rs, out, cap, st)
@@ -142,6 +207,8 @@ def test_graph_capture_replays_batch_merge_restore(cb):
     torch.cuda.synchronize()
     for rep in range(3):
         glob.fill_(-1)           # eager work between replays
+        for c in cubes:          # stale router cubes: replays must not depend on them
+            c.fill_(-1)
         out.zero_()
         torch.cuda.synchronize()
         g.replay()
