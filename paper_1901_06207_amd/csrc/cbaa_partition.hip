@@ -1,30 +1,33 @@
 // Partitioned update. The bit-sets of a batch are binned by (cube, sketch,
 // 64-bit row block) so that each bin's target -- one row block of every column
 // of one sketch, W contiguous words (128 KiB at the paper's dimensions) -- can
-// be assembled in LDS and OR-ed into the cube once, with coalesced 64-bit
-// atomic ORs. This replaces A random device-scope atomics per pair and cube
-// by a streamed 8-byte record per pair and cube.
+// be assembled in LDS and written to the cube once, coalesced. This replaces
+// A random device-scope atomics per pair and cube by a streamed 8-byte record
+// per pair and cube.
 //
-// The same seven launches serve one edge router's batch or K routers' batches
-// of uneven sizes at once (a stream table passed by value to every kernel):
-//   1. histogram   per chunk of pairs (chunks of all streams in one grid),
-//                  records per bin in LDS counters
-//   2. group sums  chunks are grouped (never across streams); per (group, bin)
-//   3. bases       per stream: bin totals, exclusive prefixes over bins of
-//                  records and of apply segments
-//   4. items       apply items prefixed over streams
-//   5. offsets     first record of every (chunk, bin) inside its stream's
-//                  record region (bins major, so a bin's records are contiguous)
-//   6. scatter     re-read each chunk, rank its records inside their bins in
-//                  LDS, stage them bin-sorted, write every bin's run
-//                  contiguously at the bin's cursor
-//   7. apply       persistent blocks walk (stream, bin, segment) items: zero
+// The same launches serve one edge router's batch or K routers' batches of
+// uneven sizes at once (a stream table passed by value to every kernel):
+//   1. histogram   per chunk of pairs (chunks of all streams in one grid):
+//                  records per bin in LDS counters, added into the stream's
+//                  bin totals
+//   2. bases       per stream: exclusive prefixes over bins of records (a
+//                  bin's records are contiguous) and of apply segments; the
+//                  bins' write cursors start at their bases
+//   3. items       apply items prefixed over streams
+//   4. scatter     persistent blocks take scatter chunks (kept in registers)
+//                  in an order that gives each XCD a contiguous range; per
+//                  cube, rank the chunk's records inside their bins in LDS,
+//                  reserve each bin's run with one atomic add on its cursor,
+//                  stage the records bin-sorted and write every run
+//                  contiguously. The order of runs inside a bin is whatever
+//                  the atomics give: the OR of the bits does not depend on it
+//   5. apply       persistent blocks walk (stream, bin, segment) items: zero
 //                  an LDS tile, OR the records' bits into it, flush non-zero
 //                  words to the stream's cube with atomic ORs -- or, for a
 //                  stream whose cubes start empty and a bin with one item,
 //                  store the whole tile (the row block needs no zeroing)
 // Fresh streams' row blocks that no single item owns (empty bins and bins
-// split over several items) are zeroed between steps 5 and 6.
+// split over several items) are zeroed before the apply.
 // A record is the mangled inner IP and the outer IP's bit with the cube index
 // in bit 31 (uint2); the apply step recomputes the columns from the mangled IP.
 #include "cbaa_internal.hpp"
@@ -34,15 +37,17 @@ namespace cbaa {
 namespace {
 
 constexpr int kBlock = 1024;
-constexpr uint32_t kChunksPerGroup = 16;  // chunks summed per thread in the scan
 constexpr uint32_t kMaxBins = 2048;
-constexpr uint32_t kStage = 16384;        // records staged in LDS per scatter step
 constexpr int kUnroll = 8;                // independent loads in flight per thread
 constexpr int kApplyUnroll = 16;
 constexpr uint32_t kMaxTileWords = 16384; // 128 KiB LDS tile
+constexpr int kScatterPer = 12;           // pairs per thread in a scatter chunk
+constexpr uint32_t kScatterChunk = kScatterPer * kBlock;
+constexpr uint32_t kScatterBlocks = 1024; // persistent scatter grid (4 per CU)
 constexpr uint32_t kDefaultChunk = 65536;
 constexpr uint32_t kDefaultSeg = 65536;
 constexpr uint32_t kDefaultApplyBlocks = 512;
+constexpr uint32_t kNoRank = 0xFFFFu;
 
 inline uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
 
@@ -52,8 +57,8 @@ struct StreamDesc {
   uint64_t* cube0;
   uint64_t* cube1;
   uint64_t rec_base;      // first record of this stream
-  uint32_t chunk_begin;   // first global chunk
-  uint32_t group_begin;   // first global group
+  uint32_t chunk_begin;   // first global histogram chunk
+  uint32_t schunk_begin;  // first global scatter chunk
   uint32_t side;
   uint32_t fresh;         // cubes start empty: row blocks are stored, not OR-ed
 };
@@ -61,16 +66,16 @@ struct StreamDesc {
 struct Batch {
   uint32_t k;
   uint32_t nbins;         // per stream: n_cubes * S * R
-  uint32_t total_chunks;
-  uint32_t total_groups;
-  uint32_t chunk;         // pairs per chunk
+  uint32_t total_chunks;  // histogram chunks of all streams
+  uint32_t total_schunks; // scatter chunks of all streams
+  uint32_t chunk;         // pairs per histogram chunk
   uint32_t seg;           // records per apply item
   StreamDesc s[CBAA_MAX_BATCH];
 };
 
 struct Layout {
-  uint32_t* counts;   // [total_chunks][nbins] -> offsets
-  uint32_t* gsum;     // [total_groups][nbins]
+  uint32_t* tot;      // [k][nbins] records per bin (summed by the histogram)
+  uint32_t* cursor;   // [k][nbins] next free record of each bin (scatter)
   uint32_t* base;     // [k][nbins + 1] record offsets inside the stream
   uint32_t* segpre;   // [k][nbins + 1] apply items inside the stream
   uint32_t* items;    // [k + 1] apply items before each stream
@@ -90,24 +95,23 @@ Tuning effective(const cbaa_tuning* t) {
   return r;
 }
 
-// Fills the batch's chunk/group/record bookkeeping and carves the scratch.
+// Fills the batch's chunk and record bookkeeping and carves the scratch.
 Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
   b.nbins = (uint32_t)n_cubes * d.S * d.R;
   b.chunk = chunk;
-  uint32_t ch = 0, gr = 0;
+  uint32_t ch = 0, sch = 0;
   uint64_t rec = 0;
   for (uint32_t i = 0; i < b.k; ++i) {
     StreamDesc& s = b.s[i];
-    const uint32_t nc = (uint32_t)((s.n + chunk - 1) / chunk);
     s.chunk_begin = ch;
-    s.group_begin = gr;
+    s.schunk_begin = sch;
     s.rec_base = rec;
-    ch += nc;
-    gr += (nc + kChunksPerGroup - 1) / kChunksPerGroup;
+    ch += (uint32_t)((s.n + chunk - 1) / chunk);
+    sch += (uint32_t)((s.n + kScatterChunk - 1) / kScatterChunk);
     rec += (uint64_t)n_cubes * s.n;
   }
   b.total_chunks = ch;
-  b.total_groups = gr;
+  b.total_schunks = sch;
   Layout L;
   uint64_t off = 0;
   char* p = (char*)base;
@@ -116,8 +120,8 @@ Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
     off += align256(bytes);
     return (void*)q;
   };
-  L.counts = (uint32_t*)take((uint64_t)(ch ? ch : 1) * b.nbins * 4);
-  L.gsum = (uint32_t*)take((uint64_t)(gr ? gr : 1) * b.nbins * 4);
+  L.tot = (uint32_t*)take((uint64_t)b.k * b.nbins * 4);
+  L.cursor = (uint32_t*)take((uint64_t)b.k * b.nbins * 4);
   L.base = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
   L.segpre = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
   L.items = (uint32_t*)take((uint64_t)(b.k + 1) * 4);
@@ -126,9 +130,9 @@ Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
   return L;
 }
 
-// Stream owning global chunk (or group) x: the last stream whose first chunk
-// (group) is <= x. Streams without chunks share their successor's start and
-// are skipped by taking the last match.
+// Stream owning global chunk x: the last stream whose first chunk is <= x
+// (streams without chunks share their successor's start and are skipped by
+// taking the last match).
 __device__ inline uint32_t owner_of_chunk(const Batch& b, uint32_t x) {
   uint32_t s = 0;
   for (uint32_t i = 1; i < b.k; ++i)
@@ -136,10 +140,10 @@ __device__ inline uint32_t owner_of_chunk(const Batch& b, uint32_t x) {
   return s;
 }
 
-__device__ inline uint32_t owner_of_group(const Batch& b, uint32_t x) {
+__device__ inline uint32_t owner_of_schunk(const Batch& b, uint32_t x) {
   uint32_t s = 0;
   for (uint32_t i = 1; i < b.k; ++i)
-    if (b.s[i].group_begin <= x) s = i;
+    if (b.s[i].schunk_begin <= x) s = i;
   return s;
 }
 
@@ -158,11 +162,16 @@ __device__ inline uint32_t bin_of_record(const Dims& d, uint2 rec) {
   return (k * d.S + (rec.x & low_mask(d.r))) * d.R + (b >> 6);
 }
 
+__global__ void k_zero_words(uint32_t* p, uint32_t n) {
+  for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+}
+
 template <bool TWO>
-__global__ __launch_bounds__(kBlock) void k_histogram(Dims d, Batch b, uint32_t* counts) {
+__global__ __launch_bounds__(kBlock) void k_histogram(Dims d, Batch b, uint32_t* tot) {
   __shared__ uint32_t hist[kMaxBins];
   const uint32_t gc = blockIdx.x;
-  const StreamDesc& st = b.s[owner_of_chunk(b, gc)];
+  const uint32_t si = owner_of_chunk(b, gc);
+  const StreamDesc& st = b.s[si];
   for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) hist[i] = 0;
   __syncthreads();
   const uint64_t lo = (uint64_t)(gc - st.chunk_begin) * b.chunk;
@@ -186,30 +195,11 @@ __global__ __launch_bounds__(kBlock) void k_histogram(Dims d, Batch b, uint32_t*
     }
   }
   __syncthreads();
-  uint32_t* row = counts + (uint64_t)gc * b.nbins;
-  for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) row[i] = hist[i];
-}
-
-// Stream and chunk range [c0, c1) of global group g.
-__device__ inline uint32_t group_chunks(const Batch& b, uint32_t g, uint32_t& c0, uint32_t& c1) {
-  const uint32_t si = owner_of_group(b, g);
-  const StreamDesc& st = b.s[si];
-  const uint32_t nc = (uint32_t)((st.n + b.chunk - 1) / b.chunk);
-  c0 = st.chunk_begin + (g - st.group_begin) * kChunksPerGroup;
-  const uint32_t end = st.chunk_begin + nc;
-  c1 = c0 + kChunksPerGroup < end ? c0 + kChunksPerGroup : end;
-  return si;
-}
-
-__global__ __launch_bounds__(256) void k_group_sums(Batch b, const uint32_t* counts, uint32_t* gsum) {
-  const uint32_t bin = blockIdx.x * 256 + threadIdx.x;
-  const uint32_t g = blockIdx.y;
-  if (bin >= b.nbins) return;
-  uint32_t c0, c1;
-  group_chunks(b, g, c0, c1);
-  uint32_t s = 0;
-  for (uint32_t c = c0; c < c1; ++c) s += counts[(uint64_t)c * b.nbins + bin];
-  gsum[(uint64_t)g * b.nbins + bin] = s;
+  uint32_t* row = tot + (uint64_t)si * b.nbins;
+  for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) {
+    const uint32_t v = hist[i];
+    if (v) __hip_atomic_fetch_add(row + i, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  }
 }
 
 // Exclusive scan of per-thread values over the block (kBlock threads).
@@ -235,17 +225,18 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_waves,
   return before + incl - v;
 }
 
-// Block si: bin totals of stream si (sum over its groups), then exclusive
-// prefixes over its bins of records (base) and apply segments (segpre).
-__global__ __launch_bounds__(kBlock) void k_bases(Batch b, const uint32_t* __restrict__ gsum,
-                                                  uint32_t* base, uint32_t* segpre) {
+// Block si: exclusive prefixes over stream si's bins of records (base, also
+// the scatter's starting cursors) and of apply segments (segpre).
+__global__ __launch_bounds__(kBlock) void k_bases(Batch b, const uint32_t* __restrict__ tot,
+                                                  uint32_t* base, uint32_t* segpre,
+                                                  uint32_t* cursor) {
   __shared__ uint32_t waves[kBlock / kWave];
   __shared__ uint32_t carry_rec, carry_seg;
   const uint32_t si = blockIdx.x;
-  const uint32_t g0 = b.s[si].group_begin;
-  const uint32_t g1 = si + 1 < b.k ? b.s[si + 1].group_begin : b.total_groups;
+  const uint32_t* t = tot + (uint64_t)si * b.nbins;
   uint32_t* bs = base + (uint64_t)si * (b.nbins + 1);
   uint32_t* sp = segpre + (uint64_t)si * (b.nbins + 1);
+  uint32_t* cu = cursor + (uint64_t)si * b.nbins;
   if (threadIdx.x == 0) {
     carry_rec = 0;
     carry_seg = 0;
@@ -253,16 +244,15 @@ __global__ __launch_bounds__(kBlock) void k_bases(Batch b, const uint32_t* __res
   __syncthreads();
   for (uint32_t b0 = 0; b0 < b.nbins; b0 += kBlock) {
     const uint32_t bin = b0 + threadIdx.x;
-    uint32_t tot = 0;
-    if (bin < b.nbins)
-      for (uint32_t g = g0; g < g1; ++g) tot += gsum[(uint64_t)g * b.nbins + bin];
-    const uint32_t nseg = (tot + b.seg - 1) / b.seg;
+    const uint32_t n = bin < b.nbins ? t[bin] : 0u;
+    const uint32_t nseg = (n + b.seg - 1) / b.seg;
     uint32_t sum_rec, sum_seg;
-    const uint32_t ex_rec = block_exclusive_scan(tot, waves, sum_rec);
+    const uint32_t ex_rec = block_exclusive_scan(n, waves, sum_rec);
     const uint32_t ex_seg = block_exclusive_scan(nseg, waves, sum_seg);
     const uint32_t cr = carry_rec, cg = carry_seg;
     if (bin < b.nbins) {
       bs[bin] = cr + ex_rec;
+      cu[bin] = cr + ex_rec;
       sp[bin] = cg + ex_seg;
     }
     __syncthreads();
@@ -288,94 +278,106 @@ __global__ void k_stream_items(Batch b, const uint32_t* segpre, uint32_t* items)
   items[b.k] = acc;
 }
 
-// counts[c][bin] <- first record (inside the stream) of chunk c in bin.
-__global__ __launch_bounds__(256) void k_offsets(Batch b, uint32_t* counts,
-                                                 const uint32_t* __restrict__ gsum,
-                                                 const uint32_t* __restrict__ base) {
-  const uint32_t bin = blockIdx.x * 256 + threadIdx.x;
-  const uint32_t g = blockIdx.y;
-  if (bin >= b.nbins) return;
-  uint32_t c0, c1;
-  const uint32_t si = group_chunks(b, g, c0, c1);
-  uint32_t run = base[(uint64_t)si * (b.nbins + 1) + bin];
-  for (uint32_t h = b.s[si].group_begin; h < g; ++h) run += gsum[(uint64_t)h * b.nbins + bin];
-  uint32_t t[kChunksPerGroup];
-#pragma unroll
-  for (uint32_t i = 0; i < kChunksPerGroup; ++i)
-    t[i] = c0 + i < c1 ? counts[(uint64_t)(c0 + i) * b.nbins + bin] : 0u;
-#pragma unroll
-  for (uint32_t i = 0; i < kChunksPerGroup; ++i) {
-    if (c0 + i < c1) counts[(uint64_t)(c0 + i) * b.nbins + bin] = run;
-    run += t[i];
-  }
+// Block x of a grid of G blocks -> virtual block. Consecutive block ids go to
+// different XCDs (round robin over 8); this gives XCD x the contiguous range
+// of virtual blocks [x*q + min(x, r), ...), so neighbouring chunks -- whose
+// runs share cache lines at bin boundaries -- are written through one L2.
+__device__ inline uint32_t xcd_major(uint32_t x, uint32_t G) {
+  const uint32_t q = G / 8, r = G % 8, xcd = x % 8, j = x / 8;
+  return xcd * q + (xcd < r ? xcd : r) + j;
 }
 
+__device__ inline uint32_t pack_rank(uint32_t rk, int u, uint32_t rank) {
+  return rk | (rank << (16 * (u & 1)));
+}
+
+__device__ inline uint32_t unpack_rank(uint32_t rk, int u) { return (rk >> (16 * (u & 1))) & 0xFFFFu; }
+
 template <bool TWO>
-__global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b,
-                                                    const uint32_t* __restrict__ offsets,
+__global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* cursor,
                                                     uint2* __restrict__ rec_all) {
-  constexpr uint32_t kPairsPerStep = TWO ? kStage / 2 : kStage;
-  constexpr int kPerThread = kPairsPerStep / kBlock;  // 8 (two cubes) or 16
-  constexpr int kRecs = TWO ? 2 * kPerThread : kPerThread;
-  __shared__ uint2 stage[kStage];
-  __shared__ uint32_t cursor[kMaxBins];
-  __shared__ uint32_t cnt[kMaxBins];
-  __shared__ uint32_t start[kMaxBins];
+  constexpr int kPer = kScatterPer;
+  constexpr uint32_t P = kScatterChunk;
+  __shared__ uint2 stage[P];
+  __shared__ uint32_t cnt[kMaxBins / 2];
+  __shared__ uint32_t start[kMaxBins / 2];
+  __shared__ uint32_t gpos[kMaxBins / 2];
   __shared__ uint32_t waves[kBlock / kWave];
-  const uint32_t gc = blockIdx.x;
-  const StreamDesc& st = b.s[owner_of_chunk(b, gc)];
-  uint2* rec = rec_all + st.rec_base;
-  const uint32_t* row = offsets + (uint64_t)gc * b.nbins;
-  for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) cursor[i] = row[i];
-  const uint64_t lo = (uint64_t)(gc - st.chunk_begin) * b.chunk;
-  const uint64_t hi = lo + b.chunk < st.n ? lo + b.chunk : st.n;
-  const int side = st.side;
-  for (uint64_t s0 = lo; s0 < hi; s0 += kPairsPerStep) {
-    for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) cnt[i] = 0;
-    __syncthreads();
-    uint2 r[kRecs];
-    uint32_t rank[kRecs];
-    uint2 p[kPerThread];
+  const uint32_t per_cube = d.S * d.R;   // bins of one cube (<= 1024)
+  const uint32_t G = gridDim.x;
+  uint2 p[kPer];
+  auto load = [&](uint32_t gc) {
+    const StreamDesc& st = b.s[owner_of_schunk(b, gc)];
+    const uint64_t lo = (uint64_t)(gc - st.schunk_begin) * P;
+    const uint32_t rem = st.n - lo < P ? (uint32_t)(st.n - lo) : P;
+    const uint2* src = st.pairs + lo;
 #pragma unroll
-    for (int u = 0; u < kPerThread; ++u) {
-      const uint64_t k = s0 + threadIdx.x + (uint64_t)u * kBlock;
-      p[u] = k < hi ? st.pairs[k] : make_uint2(0u, 0u);
+    for (int u = 0; u < kPer; ++u) {
+      const uint32_t k = threadIdx.x + u * kBlock;
+      p[u] = k < rem ? src[k] : make_uint2(0u, 0u);
     }
+  };
+  const uint32_t first = xcd_major(blockIdx.x, G);
+  if (first < b.total_schunks) load(first);
+  for (uint32_t gc = first; gc < b.total_schunks; gc += G) {
+    const uint32_t si = owner_of_schunk(b, gc);
+    const StreamDesc& st = b.s[si];
+    uint2* rec = rec_all + st.rec_base;
+    uint32_t* cur = cursor + (uint64_t)si * b.nbins;
+    const uint64_t lo = (uint64_t)(gc - st.schunk_begin) * P;
+    const uint32_t rem = st.n - lo < P ? (uint32_t)(st.n - lo) : P;
+    const int side = st.side;
 #pragma unroll
-    for (int u = 0; u < kPerThread; ++u) {
-      const bool live = s0 + threadIdx.x + (uint64_t)u * kBlock < hi;
-      const uint32_t h0 = side == CBAA_SIDE_SRC ? p[u].x : p[u].y;
-      const uint32_t p0 = side == CBAA_SIDE_SRC ? p[u].y : p[u].x;
-      const int i0 = TWO ? 2 * u : u;
-      const uint32_t bn0 = bin_of(d, 0, h0, p0, r[i0]);
-      rank[i0] = live ? atomicAdd(&cnt[bn0], 1u) : 0xFFFFFFFFu;
-      if (TWO) {
-        const uint32_t bn1 = bin_of(d, 1, p[u].y, p[u].x, r[i0 + 1]);
-        rank[i0 + 1] = live ? atomicAdd(&cnt[bn1], 1u) : 0xFFFFFFFFu;
+    for (int k = 0; k < (TWO ? 2 : 1); ++k) {
+      for (uint32_t i = threadIdx.x; i < per_cube; i += kBlock) cnt[i] = 0;
+      __syncthreads();
+      uint32_t rk[(kPer + 1) / 2];
+#pragma unroll
+      for (int u = 0; u < (kPer + 1) / 2; ++u) rk[u] = 0;
+#pragma unroll
+      for (int u = 0; u < kPer; ++u) {
+        const uint32_t h0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].x : p[u].y) : p[u].y;
+        const uint32_t p0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].y : p[u].x) : p[u].x;
+        uint2 r;
+        const uint32_t bl = bin_of(d, k, h0, p0, r) - k * per_cube;
+        const uint32_t rank = threadIdx.x + u * kBlock < rem ? atomicAdd(&cnt[bl], 1u) : kNoRank;
+        rk[u / 2] = pack_rank(rk[u / 2], u, rank);
       }
-    }
-    __syncthreads();
-    // exclusive prefix of the step's bin counts (nbins <= 2 * kBlock)
-    const uint32_t b0 = 2 * threadIdx.x;
-    const uint32_t c0 = b0 < b.nbins ? cnt[b0] : 0u;
-    const uint32_t c1 = b0 + 1 < b.nbins ? cnt[b0 + 1] : 0u;
-    uint32_t total;
-    const uint32_t ex = block_exclusive_scan(c0 + c1, waves, total);
-    if (b0 < b.nbins) start[b0] = ex;
-    if (b0 + 1 < b.nbins) start[b0 + 1] = ex + c0;
-    __syncthreads();
+      __syncthreads();
+      // local runs (exclusive prefix of the counts) and global runs (one
+      // atomic add per non-empty bin on the stream's cursor)
+      const uint32_t c0 = threadIdx.x < per_cube ? cnt[threadIdx.x] : 0u;
+      uint32_t total;
+      const uint32_t ex = block_exclusive_scan(c0, waves, total);
+      if (threadIdx.x < per_cube) {
+        start[threadIdx.x] = ex;
+        gpos[threadIdx.x] =
+            c0 ? __hip_atomic_fetch_add(cur + k * per_cube + threadIdx.x, c0, __ATOMIC_RELAXED,
+                                        __HIP_MEMORY_SCOPE_AGENT)
+               : 0u;
+      }
+      __syncthreads();
 #pragma unroll
-    for (int i = 0; i < kRecs; ++i)
-      if (rank[i] != 0xFFFFFFFFu) stage[start[bin_of_record(d, r[i])] + rank[i]] = r[i];
-    __syncthreads();
-    for (uint32_t t = threadIdx.x; t < total; t += kBlock) {
-      const uint2 v = stage[t];
-      const uint32_t bn = bin_of_record(d, v);
-      rec[cursor[bn] + (t - start[bn])] = v;
+      for (int u = 0; u < kPer; ++u) {
+        const uint32_t rank = unpack_rank(rk[u / 2], u);
+        if (rank == kNoRank) continue;
+        const uint32_t h0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].x : p[u].y) : p[u].y;
+        const uint32_t p0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].y : p[u].x) : p[u].x;
+        uint2 r;
+        const uint32_t bl = bin_of(d, k, h0, p0, r) - k * per_cube;
+        stage[start[bl] + rank] = r;
+      }
+      __syncthreads();
+      // the chunk's pairs are no longer needed: fetch the next chunk while
+      // the runs are written
+      if (k == (TWO ? 1 : 0) && gc + G < b.total_schunks) load(gc + G);
+      for (uint32_t t = threadIdx.x; t < total; t += kBlock) {
+        const uint2 v = stage[t];
+        const uint32_t bl = bin_of_record(d, v) - k * per_cube;
+        rec[gpos[bl] + (t - start[bl])] = v;
+      }
+      __syncthreads();
     }
-    __syncthreads();
-    for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) cursor[i] += cnt[i];
-    __syncthreads();
   }
 }
 
@@ -508,23 +510,21 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
     }
     return CBAA_OK;
   }
-  hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.counts);
+  const uint32_t nt = b.k * b.nbins;
+  hipLaunchKernelGGL(k_zero_words, dim3((nt + 255) / 256), dim3(256), 0, s, L.tot, nt);
+  if ((rc = check("zero launch")) != CBAA_OK) return rc;
+  hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.tot);
   if ((rc = check("histogram launch")) != CBAA_OK) return rc;
-  const dim3 sgrid((b.nbins + 255) / 256, b.total_groups);
-  hipLaunchKernelGGL(k_group_sums, sgrid, dim3(256), 0, s, b, L.counts, L.gsum);
-  if ((rc = check("group sums launch")) != CBAA_OK) return rc;
-  hipLaunchKernelGGL(k_bases, dim3(b.k), dim3(kBlock), 0, s, b, L.gsum, L.base, L.segpre);
+  hipLaunchKernelGGL(k_bases, dim3(b.k), dim3(kBlock), 0, s, b, L.tot, L.base, L.segpre, L.cursor);
   if ((rc = check("bases launch")) != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_stream_items, dim3(1), dim3(64), 0, s, b, L.segpre, L.items);
   if ((rc = check("items launch")) != CBAA_OK) return rc;
-  hipLaunchKernelGGL(k_offsets, sgrid, dim3(256), 0, s, b, L.counts, L.gsum, L.base);
-  if ((rc = check("offsets launch")) != CBAA_OK) return rc;
   if (any_fresh) {
     hipLaunchKernelGGL(k_clear_fresh, dim3(b.nbins, b.k), dim3(256), 0, s, d, b, L.segpre);
     if ((rc = check("clear launch")) != CBAA_OK) return rc;
   }
-  hipLaunchKernelGGL((k_scatter<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.counts,
-                     L.rec);
+  const uint32_t sgrid = b.total_schunks < kScatterBlocks ? b.total_schunks : kScatterBlocks;
+  hipLaunchKernelGGL((k_scatter<TWO>), dim3(sgrid), dim3(kBlock), 0, s, d, b, L.cursor, L.rec);
   if ((rc = check("scatter launch")) != CBAA_OK) return rc;
   return run_apply(d, b, L, apply_blocks, s);
 }
