@@ -15,6 +15,9 @@ constexpr int kPrepBlock = 1024;
 constexpr int kJoinBlock = 256;
 constexpr int kSortChunk = 4096;   // entries sorted per block in LDS
 constexpr int kSortBlock = 1024;
+constexpr uint32_t kSmallSort = 32768;   // lists up to this size are ranked all-pairs
+constexpr uint32_t kGatherCap = 1024;    // hot columns per (sketch, RA) list gathered
+constexpr uint64_t kGatherBytes = 256ull << 20;
 
 inline uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
 
@@ -26,6 +29,9 @@ struct RestoreScratch {
   int32_t* zmax;    // [S]
   uint32_t* hcnt;   // [S][n_ra]
   uint16_t* hot;    // [S][n_ra][maxc_ra]
+  uint32_t* gfit;   // [S][n_ra] 1 if the list was gathered into hcol
+  uint64_t* hcol;   // [S][n_ra][gcap][R] gathered hot columns, contiguous
+  uint32_t gcap;    // hot columns per list the gather buffer holds
   cbaa_host* stage; // [capacity]
   uint64_t* keys;   // [capacity]
   uint64_t bytes;
@@ -46,6 +52,13 @@ RestoreScratch carve(const Dims& d, void* base, uint64_t capacity) {
   r.zmax = (int32_t*)take((uint64_t)d.S * 4);
   r.hcnt = (uint32_t*)take((uint64_t)d.S * d.n_ra * 4);
   r.hot = (uint16_t*)take((uint64_t)d.S * d.n_ra * d.maxc_ra * 2);
+  r.gfit = (uint32_t*)take((uint64_t)d.S * d.n_ra * 4);
+  const uint64_t per_col = (uint64_t)d.S * d.n_ra * d.R * 8;
+  uint64_t gcap = kGatherBytes / per_col;
+  if (gcap > kGatherCap) gcap = kGatherCap;
+  if (gcap > d.maxc_ra) gcap = d.maxc_ra;
+  r.gcap = (uint32_t)gcap;
+  r.hcol = (uint64_t*)take(gcap * per_col);
   r.stage = (cbaa_host*)take(capacity * sizeof(cbaa_host));
   r.keys = (uint64_t*)take(capacity * 8);
   r.bytes = off;
@@ -125,11 +138,18 @@ __device__ inline int32_t sketch_threshold(const Dims& d, const uint32_t* ones, 
 
 // Block (cs, i): Zmax of sketch cs and the ascending hot-column list of RA i
 // (Alg. 2) by ordered ballot compaction. Block (cs, 0) also stores eps, Zmax.
+// A list of at most gcap columns is then copied column by column (R words
+// strided by W in the cube) into a contiguous run of hcol, where the tuple
+// join finds every hot column of the list in 512 B at the paper's g; gfit
+// records whether it was.
 __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* __restrict__ zeros,
                                                         const uint32_t* __restrict__ ones,
                                                         double* eps, int32_t* zmax, uint32_t* hcnt,
                                                         uint16_t* hot, double x, int rule,
-                                                        cbaa_restore_stats* stats) {
+                                                        cbaa_restore_stats* stats,
+                                                        const uint64_t* __restrict__ cube,
+                                                        uint64_t* hcol, uint32_t gcap,
+                                                        uint32_t* gfit) {
   __shared__ uint32_t wave_cnt[kPrepBlock / kWave];
   const uint32_t cs = blockIdx.x;
   const uint32_t i = blockIdx.y;
@@ -166,6 +186,17 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
     if (stats)
       __hip_atomic_fetch_add(&stats->hot_columns, (uint64_t)base, __ATOMIC_RELAXED,
                              __HIP_MEMORY_SCOPE_AGENT);
+  }
+  if (!hcol) return;
+  const bool fit = base <= gcap;   // base is the same in every thread
+  if (threadIdx.x == 0) gfit[cs * d.n_ra + i] = fit ? 1u : 0u;
+  if (!fit) return;
+  // the list in `out` was written by this block before the last barrier
+  const uint64_t* src = cube + (uint64_t)cs * d.R * d.W + d.aoff[i];
+  uint64_t* dst = hcol + ((uint64_t)cs * d.n_ra + i) * gcap * d.R;
+  for (uint32_t j = threadIdx.x; j < base * d.R; j += blockDim.x) {
+    const uint32_t pos = j / d.R, rb = j - pos * d.R;
+    dst[j] = src[(uint64_t)rb * d.W + out[pos]];
   }
 }
 
@@ -218,6 +249,9 @@ __device__ inline uint32_t col_zeros(const Dims& d, const Col<RPL>& c) {
 struct JoinArgs {
   const uint64_t* cube;
   const uint16_t* hot;
+  const uint64_t* hcol;   // gathered hot columns ([S][n_ra][gcap][R])
+  const uint32_t* gfit;   // [S][n_ra] list gathered
+  uint32_t gcap;
   const uint32_t* hcnt;
   const int32_t* zmax;
   const double* eps;
@@ -254,11 +288,28 @@ __device__ inline void emit_host(const Dims& d, const JoinArgs& ja, uint32_t cs,
   }
 }
 
+// Column `col` at position `pos` of the hot list of RA `level` in sketch cs:
+// from the gathered copy (G) or straight from the cube.
+template <int RPL, bool G>
+__device__ inline void load_hot(const Dims& d, const JoinArgs& ja, uint32_t cs, uint32_t level,
+                                uint32_t pos, uint32_t col, Col<RPL>& c) {
+  if constexpr (G) {
+    const uint64_t* src = ja.hcol + (((uint64_t)cs * d.n_ra + level) * ja.gcap + pos) * d.R;
+#pragma unroll
+    for (int q = 0; q < RPL; ++q) {
+      const uint32_t rb = lane_id() + q * kWave;
+      c.w[q] = rb < d.R ? src[rb] : ~0ull;
+    }
+  } else {
+    load_col<RPL>(d, ja.cube, cs, d.aoff[level] + col, c);
+  }
+}
+
 // Candidates that pass the CP screen are taken kBatch at a time so their
 // column loads are in flight together.
 constexpr int kBatch = 4;
 
-template <int NRA, int NVA, int RPL, int LEVEL>
+template <int NRA, int NVA, int RPL, int LEVEL, bool G>
 __device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t zm,
                        uint32_t (&t)[NRA], const Col<RPL>& acc, uint32_t& n_partial,
                        uint32_t& n_tuples) {
@@ -274,22 +325,24 @@ __device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t z
     if (LEVEL == NRA - 1) ok = ok && (cand >> d.ep[LEVEL]) == want_hi;
     uint64_t m = __ballot(ok);
     while (m) {
-      uint32_t h[kBatch];
+      uint32_t h[kBatch], pos[kBatch];
       int nb = 0;
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         h[q] = 0;
+        pos[q] = 0;
         if (m) {
           const int l = __builtin_ctzll(m);
           m &= m - 1;
           h[q] = (uint32_t)__builtin_amdgcn_readlane((int)cand, l);
+          pos[q] = base + (uint32_t)l;
           nb = q + 1;
         }
       }
       Col<RPL> c[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q)
-        if (q < nb) load_col<RPL>(d, ja.cube, cs, d.aoff[LEVEL] + h[q], c[q]);
+        if (q < nb) load_hot<RPL, G>(d, ja, cs, LEVEL, pos[q], h[q], c[q]);
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         if (q >= nb) break;
@@ -299,7 +352,7 @@ __device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t z
         if constexpr (LEVEL < NRA - 1) {
           ++n_partial;
           if ((int32_t)col_zeros<RPL>(d, c[q]) > zm) continue;
-          extend<NRA, NVA, RPL, LEVEL + 1>(d, ja, cs, zm, t, c[q], n_partial, n_tuples);
+          extend<NRA, NVA, RPL, LEVEL + 1, G>(d, ja, cs, zm, t, c[q], n_partial, n_tuples);
         } else {
           // complete CP-valid tuple: LP = concatenation of the EPs
           uint32_t lp = 0;
@@ -321,9 +374,16 @@ __device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t z
   }
 }
 
-template <int NRA, int NVA, int RPL>
+// G: the variant that reads gathered columns. Both variants are launched;
+// each first checks whether every hot list fit the gather buffer and only
+// the matching one proceeds (the test is uniform over the grid).
+template <int NRA, int NVA, int RPL, bool G>
 __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
   __shared__ uint32_t pre[257];
+  uint32_t missed = 0;
+  for (uint32_t i = lane_id(); i < d.S * NRA; i += kWave) missed |= ja.gfit[i] ^ 1u;
+  const bool all_fit = __ballot(missed != 0) == 0;
+  if (all_fit != G) return;
   // prefix over sketches of |HC(0)|: flattened work list of (cs, hc0)
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
@@ -346,13 +406,14 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
       if (pre[mid] <= item) lo = mid; else hi = mid;
     }
     const uint32_t cs = lo;
-    const uint32_t hc0 = ja.hot[((uint64_t)cs * NRA + 0) * d.maxc_ra + (item - pre[cs])];
+    const uint32_t pos0 = item - pre[cs];
+    const uint32_t hc0 = ja.hot[((uint64_t)cs * NRA + 0) * d.maxc_ra + pos0];
     const int32_t zm = ja.zmax[cs];
     uint32_t t[NRA];
     t[0] = hc0;
     Col<RPL> c0;
-    load_col<RPL>(d, ja.cube, cs, d.aoff[0] + hc0, c0);
-    extend<NRA, NVA, RPL, 1>(d, ja, cs, zm, t, c0, n_partial, n_tuples);
+    load_hot<RPL, G>(d, ja, cs, 0, pos0, hc0, c0);
+    extend<NRA, NVA, RPL, 1, G>(d, ja, cs, zm, t, c0, n_partial, n_tuples);
   }
   if (lane_id() == 0 && (n_partial | n_tuples)) {
     __hip_atomic_fetch_add(&ja.stats->partial_checked, (uint64_t)n_partial, __ATOMIC_RELAXED,
@@ -368,11 +429,30 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
 // (bitonic); a second kernel ranks every key against the other chunks by
 // binary search and scatters the entry to its final place.
 
+// Lists of at most kSmallSort entries: one wave per entry counts the smaller
+// keys over the whole list and writes the entry at that rank.
+__global__ __launch_bounds__(256) void k_rank_small(const cbaa_host* __restrict__ stage,
+                                                    const cbaa_restore_stats* stats,
+                                                    uint64_t capacity, cbaa_host* out) {
+  const uint64_t n = stats->n_hosts < capacity ? stats->n_hosts : capacity;
+  if (n > kSmallSort) return;
+  const uint32_t e = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
+  if (e >= n) return;
+  const uint64_t key = ((uint64_t)stage[e].ip << 32) | e;
+  uint32_t less = 0;
+  for (uint32_t j = lane_id(); j < n; j += kWave)
+    less += (((uint64_t)stage[j].ip << 32) | j) < key ? 1u : 0u;
+  const uint32_t rank = wave_sum(less);
+  if (lane_id() == 0) out[rank] = stage[e];
+}
+
+// Larger lists: chunks sorted in LDS, then ranked across chunks.
 __global__ __launch_bounds__(kSortBlock) void k_sort_chunks(const cbaa_host* stage,
                                                             const cbaa_restore_stats* stats,
                                                             uint64_t capacity, uint64_t* keys) {
   __shared__ uint64_t k[kSortChunk];
   const uint64_t n = stats->n_hosts < capacity ? stats->n_hosts : capacity;
+  if (n <= kSmallSort) return;
   const uint64_t base = (uint64_t)blockIdx.x * kSortChunk;
   if (base >= n) return;
   const uint32_t m = (uint32_t)(n - base < kSortChunk ? n - base : kSortChunk);
@@ -392,6 +472,7 @@ __global__ __launch_bounds__(256) void k_rank_scatter(const cbaa_host* stage, co
                                                       const cbaa_restore_stats* stats,
                                                       uint64_t capacity, cbaa_host* out) {
   const uint64_t n = stats->n_hosts < capacity ? stats->n_hosts : capacity;
+  if (n <= kSmallSort) return;
   const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (g >= n) return;
   const uint64_t key = keys[g];
@@ -517,7 +598,9 @@ int dispatch_rpl_join(const Dims& d, const JoinArgs& ja, hipStream_t s) {
   const uint32_t grid = 2048;  // 8 waves per CU on 256 CUs; waves stride over the work list
 #define CBAA_JOIN(RPL)                                                                  \
   if (d.R <= RPL * kWave) {                                                             \
-    hipLaunchKernelGGL((k_join<NRA, NVA, RPL>), dim3(grid / (kJoinBlock / kWave)),      \
+    hipLaunchKernelGGL((k_join<NRA, NVA, RPL, true>), dim3(grid / (kJoinBlock / kWave)), \
+                       dim3(kJoinBlock), 0, s, d, ja);                                  \
+    hipLaunchKernelGGL((k_join<NRA, NVA, RPL, false>), dim3(grid / (kJoinBlock / kWave)),\
                        dim3(kJoinBlock), 0, s, d, ja);                                  \
     return check_launch("join launch");                                                \
   }
@@ -604,11 +687,17 @@ int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void
   int rc = run_scan(d, cube, rs.zeros, rs.ones, stats, s);
   if (rc != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, d.n_ra), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
-                     rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats);
+                     rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats, cube, rs.hcol, rs.gcap,
+                     rs.gfit);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
-  JoinArgs ja{cube, rs.hot, rs.hcnt, rs.zmax, rs.eps, rs.stage, capacity, stats};
+  JoinArgs ja{cube, rs.hot, rs.hcol, rs.gfit, rs.gcap, rs.hcnt, rs.zmax, rs.eps, rs.stage,
+              capacity, stats};
   if ((rc = run_join(d, ja, s)) != CBAA_OK) return rc;
   if (capacity == 0) return CBAA_OK;
+  const uint64_t small = capacity < kSmallSort ? capacity : kSmallSort;
+  hipLaunchKernelGGL(k_rank_small, dim3((uint32_t)((small + 3) / 4)), dim3(256), 0, s, rs.stage,
+                     stats, capacity, out);
+  if ((rc = check_launch("rank launch")) != CBAA_OK) return rc;
   const uint32_t nchunks = (uint32_t)((capacity + kSortChunk - 1) / kSortChunk);
   hipLaunchKernelGGL(k_sort_chunks, dim3(nchunks), dim3(kSortBlock), 0, s, rs.stage, stats,
                      capacity, rs.keys);
@@ -626,7 +715,8 @@ int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, 
   if (rc != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, 1), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
                      rs.eps, rs.zmax, rs.hcnt, (uint16_t*)nullptr, 1.0, CBAA_THR_THM2,
-                     (cbaa_restore_stats*)nullptr);
+                     (cbaa_restore_stats*)nullptr, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                     0u, (uint32_t*)nullptr);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
   return run_est(d, cube, hosts, n, rs.eps, est, zeros, layer_zeros, s);
 }
@@ -638,7 +728,8 @@ int launch_features(const Dims& d, const uint64_t* cube, const uint32_t* hosts, 
   if (rc != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, 1), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
                      rs.eps, rs.zmax, rs.hcnt, (uint16_t*)nullptr, 1.0, CBAA_THR_THM2,
-                     (cbaa_restore_stats*)nullptr);
+                     (cbaa_restore_stats*)nullptr, (const uint64_t*)nullptr, (uint64_t*)nullptr,
+                     0u, (uint32_t*)nullptr);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
   return run_feat(d, cube, hosts, n, rs.eps, F, x, s);
 }

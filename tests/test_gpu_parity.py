@@ -273,6 +273,57 @@ def test_restore_saturated_host(cb):
     assert got["flags"][got["ip"] == host][0] == cb.FLAG_SATURATED
 
 
+def _cube_from_numpy(cube_np):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(cube_np).view(np.int64)).cuda()
+
+
+def _set_columns(p, cube_np, cs, a, cols):
+    """All g bits of the listed columns of array a in sketch cs."""
+    g = 1 << p["log2_g"]
+    R = g // 64
+    ncol = [1 << c for c in p["cbn"][: p["n_ra"] + p["n_va"]]]
+    W = sum(ncol)
+    aoff = int(sum(ncol[:a]))
+    for rb in range(R):
+        cube_np[(cs * R + rb) * W + aoff + np.asarray(cols)] = np.uint64(0xFFFFFFFFFFFFFFFF)
+
+
+def test_restore_long_hot_list_on_the_trace_cube(cb):
+    """A window cube whose RA 0 in sketch 3 has 1500 saturated columns: that
+    hot list no longer fits the per-list gather buffer, so the join reads the
+    cube directly; the result is the oracle's."""
+    p = default_params()
+    t = tracegen.window_small(2)
+    cube_np = O.cube_of(p, t.pairs, 0).copy()
+    _set_columns(p, cube_np, 3, 0, np.arange(1000, 2500))
+    _say("long hot list")
+    got, st = cb.restore(p, _cube_from_numpy(cube_np), 1024.0)
+    want, wst = O.restore(p, cube_np, 1024.0)
+    assert st["hot_columns"] == wst["hot_columns"] and wst["hot_columns"] > 1500
+    _assert_hosts_equal(got, want)
+
+
+def test_restore_tens_of_thousands_of_hosts(cb):
+    """Sketch 0 with RA 0, RA 1 and the VA fully set and one RA 2 column set:
+    every LP with that RA 2 column restores (2^(28-12) = 65536 hosts, all
+    saturated), which takes the long-list join and the large-list sort."""
+    p = default_params()
+    g = 1 << p["log2_g"]
+    words = (1 << p["r"]) * (g // 64) * sum(1 << c for c in p["cbn"][:4])
+    cube_np = np.zeros(words, np.uint64)
+    _set_columns(p, cube_np, 0, 0, np.arange(4096))
+    _set_columns(p, cube_np, 0, 1, np.arange(4096))
+    _set_columns(p, cube_np, 0, 2, [1234])
+    _set_columns(p, cube_np, 0, 3, np.arange(4096))
+    _say("65536 hosts")
+    got, st = cb.restore(p, _cube_from_numpy(cube_np), 1024.0)
+    want, _ = O.restore(p, cube_np, 1024.0)
+    assert want.size == 65536
+    _assert_hosts_equal(got, want)
+    assert np.all(np.diff(got["ip"].astype(np.int64)) > 0)
+
+
 # ---------------------------------------------------------------- estimate
 
 def test_estimate_matches_oracle(cb):
