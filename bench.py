@@ -485,10 +485,13 @@ def bench_learned(cfg, trace, g_src, local, dev, args):
     x_te = learned.features(cfg, g_src, hosts[te])
     est_ml = learned.predict(model, x_te).cpu().numpy()
     est_lc = learned.linear_count(cfg, g_src, hosts[te])
-    rep = learned.compare(est_lc, est_ml, counts[te], args.theta)
+    est_row = learned.row_aware_count(x_te).cpu().numpy()
+    rep = learned.compare(est_lc, est_ml, counts[te], args.theta, est_row=est_row)
     return {"train_rows": int(tr.size), "test_rows": int(te.size), "epochs": tl.epochs,
+            "features": int(x_tr.shape[1]),
             "train_s": round(train_s, 2), "final_loss": round(tl.final_loss, 5),
             "lc": {k: round(v, 5) for k, v in rep["lc"].items()},
+            "row": {k: round(v, 5) for k, v in rep["row"].items()},
             "mlp": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep["mlp"].items()},
             "bins": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in b.items()}
                      for b in rep["bins"]]}

@@ -22,7 +22,13 @@
  * array a, x[a] = ln(1 + g u_a), u_a = -ln(max(z_a, 1) / g), z_a = g - the
  * popcount of the host's column in array a; with F = n_ra + n_va + 2 also the
  * union column's ln(1 + g u), u = max(0, -ln(max(Z, 1) / (g - g eps))) (Thm. 2),
- * and g eps (Thm. 1). Logarithms in fp64, stored as fp32.
+ * and g eps (Thm. 1); with F = n_ra + n_va + 4 further the union column's
+ * ln(1 + g u) with g eps replaced by the sketch's row-aware shared-bit mass
+ * M = sum over rows b of prod over arrays a of (columns of a with bit b set)
+ * / c(a), and M itself. M extends Thm. 1 to rows that fill unevenly (it is
+ * g eps when every row of an array is equally full); the rows fan-in hosts
+ * set in almost every column are what it captures. Logarithms in fp64,
+ * stored as fp32.
  *
  * Conventions as in cbaa.h: device pointers, caller-owned buffers, stream as
  * void*, CBAA_* return codes, asynchronous enqueue.
@@ -47,8 +53,9 @@ uint32_t cbaa_mlp_param_count(uint32_t n_features);
 int cbaa_mlp_init(uint32_t n_features, uint32_t seed, int zero_output, float* d_master,
                   uint16_t* d_wbf, void* stream);
 
-/* Per-host features from a cube (see above). n_features is n_ra + n_va or
- * n_ra + n_va + 2. d_scratch holds cbaa_restore_scratch_bytes(cfg, 0). */
+/* Per-host features from a cube (see above). n_features is n_ra + n_va,
+ * n_ra + n_va + 2 or n_ra + n_va + 4 (at most 8). d_scratch holds
+ * cbaa_restore_scratch_bytes(cfg, 0). */
 int cbaa_mlp_features(const cbaa_config* h_cfg, const void* d_cube, const uint32_t* d_hosts,
                       uint64_t n, uint32_t n_features, float* d_x, void* d_scratch,
                       uint64_t scratch_bytes, void* stream);

@@ -85,6 +85,8 @@ def _load():
         "ref_estimate": (None, [cfgp, u64p, u32p, C.c_uint64, f64p, u16p, u8p]),
         "ref_host_layer_zeros": (None, [cfgp, u64p, u32p, C.c_uint64, u16p]),
         "ref_exact_counts": (C.c_uint64, [u32p, C.c_uint64, C.c_int, u32p, u32p]),
+        "ref_row_ones": (None, [cfgp, u64p, u32p]),
+        "ref_row_shared": (None, [cfgp, u32p, f64p]),
         "ref_check_mangle_bijection": (C.c_uint64, [cfgp]),
         "ref_check_lp_roundtrip": (C.c_uint64, [cfgp]),
         "ref_tuple_check": (C.c_int, [cfgp, u32p, P(C.c_uint32)]),
@@ -190,6 +192,22 @@ def column_zeros(p: dict, cube: np.ndarray) -> tuple[np.ndarray, np.ndarray]:
     ones = np.zeros(S * A, np.uint32)
     _load().ref_column_zeros(C.byref(_cfg(p)), _ptr(cube), _ptr(zeros), _ptr(ones))
     return zeros, ones
+
+
+def row_ones(p: dict, cube: np.ndarray) -> np.ndarray:
+    """uint32 [2^r, |RA|+|VA|, g]: columns of each array with each bit set."""
+    S, A, g = 1 << p["r"], p["n_ra"] + p["n_va"], 1 << p["log2_g"]
+    out = np.zeros(S * A * g, np.uint32)
+    _load().ref_row_ones(C.byref(_cfg(p)), _ptr(cube), _ptr(out))
+    return out.reshape(S, A, g)
+
+
+def row_shared(p: dict, rows: np.ndarray) -> np.ndarray:
+    """fp64 [2^r]: sum over rows of the product over arrays of row fill."""
+    rows = np.ascontiguousarray(rows, dtype=np.uint32)
+    out = np.zeros(1 << p["r"], np.float64)
+    _load().ref_row_shared(C.byref(_cfg(p)), _ptr(rows), _ptr(out))
+    return out
 
 
 def thresholds(p: dict, ones: np.ndarray, theta: float, rule: int = THR_THM2):

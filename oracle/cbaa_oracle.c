@@ -15,6 +15,9 @@
  *   - reassembly LP || RP and unmangling            (Sec. 3.1 mangling, end of Sec. 3.3)
  *   - the corrected linear-counting estimate        (Eq. 1, Thm. 2)
  *   - exact per-host distinct-peer counts           (Sec. 3.1 "exact way"; Sec. 5.1 baseline)
+ *   - per-row fills and the row-aware shared-bit mass (an extension of Thm. 1
+ *     used by the learned estimator; it reduces to g * eps when every row of
+ *     an array is equally full)
  *
  * Only tests/, the smoke entry and the benchmark's CPU-baseline leg may load
  * this library. It shares no code with the HIP library: no header, no helper,
@@ -600,6 +603,52 @@ void ref_host_layer_zeros(const ref_config* c, const uint64_t* cube, const uint3
       read_column(&l, cube, cs, a, cols[a], buf);
       layer_zeros[k * A + a] = (uint16_t)column_zeros(&l, buf);
     }
+  }
+}
+
+/* ------------------------------------------------------------------ */
+/* Row fills (extension of Thm. 1 for the learned estimator)             */
+/* ------------------------------------------------------------------ */
+
+/* row_ones[(cs * A + a) * g + b] = number of columns of array a in sketch cs
+ * whose bit b is set. Thm. 1 takes every row of an array to be set with the
+ * same probability; these counts are what that probability is per row. */
+void ref_row_ones(const ref_config* c, const uint64_t* cube, uint32_t* row_ones) {
+  layout l = layout_of(c);
+  uint32_t A = n_arrays(c);
+  uint64_t g = g_bits(c);
+  memset(row_ones, 0, sizeof(uint32_t) * (size_t)((1u << c->r) * A * g));
+  for (uint32_t cs = 0; cs < (1u << c->r); ++cs)
+    for (uint32_t a = 0; a < A; ++a)
+      for (uint32_t col = 0; col < n_cols(c, a); ++col)
+        for (uint32_t rb = 0; rb < l.R; ++rb) {
+          /* each one bit of this word of the column is one row */
+          uint64_t w = cube[word_index(&l, cs, a, col, rb * 64u)];
+          while (w) {
+            uint32_t bit = (uint32_t)__builtin_ctzll(w);
+            row_ones[((uint64_t)cs * A + a) * g + rb * 64u + bit] += 1;
+            w &= w - 1;
+          }
+        }
+}
+
+/* Row-aware shared-bit mass of each sketch: the sum over rows b of the
+ * product over arrays (in array order) of row_ones / c(a). It is the
+ * expected number of one bits in the union column of an inner IP the window
+ * never saw when rows fill unevenly; with every row of an array equally full
+ * it equals g * eps of Thm. 1. */
+void ref_row_shared(const ref_config* c, const uint32_t* row_ones, double* shared) {
+  uint32_t A = n_arrays(c);
+  uint64_t g = g_bits(c);
+  for (uint32_t cs = 0; cs < (1u << c->r); ++cs) {
+    double s = 0.0;
+    for (uint64_t b = 0; b < g; ++b) {
+      double q = 1.0;
+      for (uint32_t a = 0; a < A; ++a)
+        q = q * ((double)row_ones[((uint64_t)cs * A + a) * g + b] / (double)n_cols(c, a));
+      s += q;
+    }
+    shared[cs] = s;
   }
 }
 

@@ -16,7 +16,10 @@ master copy); biases in fp32. Flat parameter order:
     W1 [64, F] row-major, b1 [64], W2 [64, 64] row-major, b2 [64], w3 [64], b3 [1]
 Features (see ``features``): each array's own linear count of the host's
 column in log form, ln(1 + g u_a) with u_a = -ln(max(z_a, 1)/g), optionally
-followed by the union column's Thm. 2 count in the same form and g * eps.
+followed by the union column's Thm. 2 count in the same form and g * eps,
+and optionally by the union column's count against the row-aware shared-bit
+mass (sum over rows of the product of row fills, see row_shared in the CBAA
+oracle) in the same form and that mass.
 
 Parity unpinned for the training outcome itself (it depends on data); the
 gradient is pinned by central finite differences.
@@ -30,19 +33,24 @@ H = 64
 
 
 def features(layer_zeros: np.ndarray, union_zeros: np.ndarray, eps: np.ndarray, g: int,
-             extended: bool = True) -> np.ndarray:
-    """Features from per-array zero counts [n, A], union-column zeros [n] and
-    the hosts' sketch eps [n] (fp64 arithmetic, fp32 result)."""
+             extended: bool = True, shared: np.ndarray | None = None) -> np.ndarray:
+    """Features from per-array zero counts [n, A], union-column zeros [n],
+    the hosts' sketch eps [n] and, for the row-aware pair, the hosts' sketch
+    shared-bit mass [n] (fp64 arithmetic, fp32 result)."""
     g = float(g)
 
     def logcount(z, denom):
-        u = -np.log(np.maximum(z.astype(np.float64), 1.0) / denom)
+        with np.errstate(divide="ignore"):
+            u = -np.log(np.maximum(z.astype(np.float64), 1.0) / denom)
         return np.log1p(g * np.maximum(u, 0.0))
 
     cols = [logcount(layer_zeros[:, a], g) for a in range(layer_zeros.shape[1])]
     if extended:
         cols.append(logcount(union_zeros, g - g * eps))
         cols.append(g * eps)
+    if shared is not None:
+        cols.append(logcount(union_zeros, g - shared))
+        cols.append(shared)
     return np.stack(cols, axis=1).astype(np.float32)
 
 

@@ -323,7 +323,8 @@ int cbaa_mlp_features(const cbaa_config* cfg, const void* d_cube, const uint32_t
                       uint64_t scratch_bytes, void* stream) {
   CHECK_DIMS(cfg, d);
   REQUIRE(d_cube && ((uintptr_t)d_cube & 15u) == 0, "cube must be 16-byte aligned");
-  REQUIRE(n_features == d.A || n_features == d.A + 2, "n_features must be A or A + 2");
+  REQUIRE(n_features == d.A || n_features == d.A + 2 || n_features == d.A + 4,
+          "n_features must be A, A + 2 or A + 4");
   REQUIRE(n_features <= 8, "at most 8 features");
   REQUIRE(d_scratch && ((uintptr_t)d_scratch & 255u) == 0, "scratch must be 256-byte aligned");
   if (scratch_bytes < restore_scratch_bytes(d, 0)) {

@@ -32,6 +32,8 @@ struct RestoreScratch {
   uint32_t* gfit;   // [S][n_ra] 1 if the list was gathered into hcol
   uint64_t* hcol;   // [S][n_ra][gcap][R] gathered hot columns, contiguous
   uint32_t gcap;    // hot columns per list the gather buffer holds
+  uint32_t* rows;   // [S][A][g] columns of each array with each bit set (features)
+  double* shared;   // [S] row-aware shared-bit mass (features)
   cbaa_host* stage; // [capacity]
   uint64_t* keys;   // [capacity]
   uint64_t bytes;
@@ -59,6 +61,8 @@ RestoreScratch carve(const Dims& d, void* base, uint64_t capacity) {
   if (gcap > d.maxc_ra) gcap = d.maxc_ra;
   r.gcap = (uint32_t)gcap;
   r.hcol = (uint64_t*)take(gcap * per_col);
+  r.rows = (uint32_t*)take((uint64_t)d.S * d.A * d.g * 4);
+  r.shared = (double*)take((uint64_t)d.S * 8);
   r.stage = (cbaa_host*)take(capacity * sizeof(cbaa_host));
   r.keys = (uint64_t*)take(capacity * 8);
   r.bytes = off;
@@ -544,7 +548,8 @@ __device__ inline float log_count_feature(double g, uint32_t z, double denom) {
 template <int NRA, int NVA, int RPL>
 __global__ __launch_bounds__(256) void k_features(Dims d, const uint64_t* __restrict__ cube,
                                                   const uint32_t* __restrict__ hosts, uint64_t n,
-                                                  const double* __restrict__ eps, uint32_t F,
+                                                  const double* __restrict__ eps,
+                                                  const double* __restrict__ shared, uint32_t F,
                                                   float* x) {
   constexpr int A = NRA + NVA;
   const uint64_t gw = ((uint64_t)blockIdx.x * blockDim.x + threadIdx.x) / kWave;
@@ -566,12 +571,81 @@ __global__ __launch_bounds__(256) void k_features(Dims d, const uint64_t* __rest
       for (int q = 0; q < RPL; ++q) u.w[q] &= c.w[q];
     }
     const uint32_t z = col_zeros<RPL>(d, u);
-    if (lane_id() == 0 && F == (uint32_t)A + 2) {
+    if (lane_id() == 0 && F >= (uint32_t)A + 2) {
       const double e = eps[cs];
       x[k * F + A] = log_count_feature(g, z, g - g * e);
       x[k * F + A + 1] = (float)(g * e);
     }
+    if (lane_id() == 0 && F == (uint32_t)A + 4) {
+      const double sh = shared[cs];
+      x[k * F + A + 2] = log_count_feature(g, z, g - sh);
+      x[k * F + A + 3] = (float)sh;
+    }
   }
+}
+
+// ---- per-row fills (features) ------------------------------------------
+// Block (cs, rb): for every array a and each of the 64 rows of row block rb,
+// the number of a's columns with that bit set. A wave reads 64 neighbouring
+// words (one per lane); for bit j, the ballot of "bit j set" restricted to the
+// lanes of array a, popcounted, is that chunk's count, kept by lane j.
+constexpr int kRowBlock = 256;
+
+__global__ __launch_bounds__(kRowBlock) void k_row_ones(Dims d, const uint64_t* __restrict__ cube,
+                                                        uint32_t* rows) {
+  __shared__ uint32_t cnt[CBAA_MAX_ARRAYS * kWave];
+  const uint32_t cs = blockIdx.x / d.R, rb = blockIdx.x % d.R;
+  for (uint32_t i = threadIdx.x; i < d.A * kWave; i += kRowBlock) cnt[i] = 0;
+  __syncthreads();
+  const uint64_t* base = cube + ((uint64_t)cs * d.R + rb) * d.W;
+  const uint32_t wid = threadIdx.x / kWave, lane = lane_id();
+  for (uint32_t c0 = wid * kWave; c0 < d.W; c0 += kRowBlock) {
+    const uint32_t w = c0 + lane;
+    const bool valid = w < d.W;
+    const uint64_t word = valid ? base[w] : 0ull;
+    uint32_t arr = d.A;
+    for (uint32_t a = 0; a < d.A; ++a)
+      if (valid && w >= d.aoff[a] && w < d.aoff[a] + d.ncol[a]) arr = a;
+    const uint32_t last = d.W - 1 - c0 < (uint32_t)(kWave - 1) ? d.W - 1 - c0 : (uint32_t)(kWave - 1);
+    const uint32_t a_lo = (uint32_t)__builtin_amdgcn_readfirstlane((int)arr);
+    const uint32_t a_hi = (uint32_t)__builtin_amdgcn_readlane((int)arr, (int)last);
+    for (uint32_t a = a_lo; a <= a_hi; ++a) {
+      const uint64_t amask = __ballot(arr == a);
+      uint32_t mine = 0;
+      for (uint32_t j = 0; j < (uint32_t)kWave; ++j) {
+        const uint32_t c = (uint32_t)__popcll(__ballot((word >> j) & 1ull) & amask);
+        if (lane == j) mine = c;
+      }
+      if (mine) atomicAdd(&cnt[a * kWave + lane], mine);
+    }
+  }
+  __syncthreads();
+  for (uint32_t i = threadIdx.x; i < d.A * kWave; i += kRowBlock) {
+    const uint32_t a = i / kWave, j = i % kWave;
+    rows[((uint64_t)cs * d.A + a) * d.g + rb * kWave + j] = cnt[i];
+  }
+}
+
+// Block cs: sum over rows of the product over arrays (in array order) of
+// row_ones / c(a) -- the row-aware counterpart of g * eps.
+__global__ __launch_bounds__(kRowBlock) void k_row_shared(Dims d, const uint32_t* __restrict__ rows,
+                                                          double* shared) {
+  __shared__ double part[kRowBlock];
+  const uint32_t cs = blockIdx.x;
+  double s = 0.0;
+  for (uint32_t b = threadIdx.x; b < d.g; b += kRowBlock) {
+    double q = 1.0;
+    for (uint32_t a = 0; a < d.A; ++a)
+      q = q * ((double)rows[((uint64_t)cs * d.A + a) * d.g + b] / (double)d.ncol[a]);
+    s += q;
+  }
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (uint32_t o = kRowBlock / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < o) part[threadIdx.x] += part[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) shared[cs] = part[0];
 }
 
 int check_launch(const char* what) {
@@ -646,13 +720,14 @@ int run_join(const Dims& d, const JoinArgs& ja, hipStream_t s) {
 
 template <int NRA, int NVA>
 int dispatch_rpl_feat(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
-                      const double* eps, uint32_t F, float* x, hipStream_t s) {
+                      const double* eps, const double* shared, uint32_t F, float* x,
+                      hipStream_t s) {
   uint64_t blocks = (n + 3) / 4;
   if (blocks > 4096) blocks = 4096;
 #define CBAA_FEAT(RPL)                                                                       \
   if (d.R <= RPL * kWave) {                                                                  \
     hipLaunchKernelGGL((k_features<NRA, NVA, RPL>), dim3((uint32_t)blocks), dim3(256), 0, s, \
-                       d, cube, hosts, n, eps, F, x);                                        \
+                       d, cube, hosts, n, eps, shared, F, x);                                \
     return check_launch("features launch");                                                 \
   }
   CBAA_FEAT(1) CBAA_FEAT(2) CBAA_FEAT(4) CBAA_FEAT(8)
@@ -661,8 +736,8 @@ int dispatch_rpl_feat(const Dims& d, const uint64_t* cube, const uint32_t* hosts
 }
 
 int run_feat(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
-             const double* eps, uint32_t F, float* x, hipStream_t s) {
-  CBAA_ARRAY_DISPATCH(dispatch_rpl_feat, d, cube, hosts, n, eps, F, x, s);
+             const double* eps, const double* shared, uint32_t F, float* x, hipStream_t s) {
+  CBAA_ARRAY_DISPATCH(dispatch_rpl_feat, d, cube, hosts, n, eps, shared, F, x, s);
 }
 
 int run_est(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
@@ -731,7 +806,13 @@ int launch_features(const Dims& d, const uint64_t* cube, const uint32_t* hosts, 
                      (cbaa_restore_stats*)nullptr, (const uint64_t*)nullptr, (uint64_t*)nullptr,
                      0u, (uint32_t*)nullptr);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
-  return run_feat(d, cube, hosts, n, rs.eps, F, x, s);
+  if (F == d.A + 4) {
+    hipLaunchKernelGGL(k_row_ones, dim3(d.S * d.R), dim3(kRowBlock), 0, s, d, cube, rs.rows);
+    if ((rc = check_launch("row fill launch")) != CBAA_OK) return rc;
+    hipLaunchKernelGGL(k_row_shared, dim3(d.S), dim3(kRowBlock), 0, s, d, rs.rows, rs.shared);
+    if ((rc = check_launch("row mass launch")) != CBAA_OK) return rc;
+  }
+  return run_feat(d, cube, hosts, n, rs.eps, rs.shared, F, x, s);
 }
 
 }  // namespace cbaa

@@ -4,11 +4,19 @@ torch only holds device buffers).
 
 The network reads a host's per-array column popcounts in the log domain of
 the linear count, plus its union column's Thm. 2 count and its sketch's
-g*eps (features of cbaa_mlp_features), and outputs a correction in log space
-of the paper's estimate: ln(1 + n_hat) = x_uc + y, where x_uc = ln(1 + Thm. 2
-estimate) is the union-column feature. A network whose output is zero is the
-paper's estimator, which therefore stays both the starting point and the
-fallback. Labels are supplied by the caller.
+g*eps, and (full feature set) the union column's count against the sketch's
+row-aware shared-bit mass and that mass (features of cbaa_mlp_features). It
+outputs a correction in log space of the union-column count that comes last
+among them: ln(1 + n_hat) = x_base + y, x_base being the row-aware count with
+the full set, Thm. 2's with the shorter one. A network whose output is zero is
+that count, which therefore stays both the starting point and the fallback.
+Labels are supplied by the caller.
+
+The row-aware count replaces Thm. 1's uniform shared-bit probability by a
+per-row one: q_b = product over arrays of the fraction of columns with bit b
+set, summed over the g rows (it equals g*eps when rows fill evenly). Fan-in
+super hosts set their own row in nearly every column, which Thm. 1 cannot
+see; the row-aware count subtracts exactly those rows.
 """
 
 from __future__ import annotations
@@ -30,7 +38,7 @@ class Model:
 
     @classmethod
     def new(cls, n_features: int, seed: int = 1, device="cuda") -> "Model":
-        """A fresh network for the extended features (n_ra + n_va + 2)."""
+        """A fresh network for extended features (n_ra + n_va + 2 or + 4)."""
         P = cbaa.cbaa_mlp_param_count(n_features)
         if P == 0 or n_features < 3:
             raise ValueError("3 <= n_features <= 8 (extended features)")
@@ -44,10 +52,12 @@ class Model:
         return {"n_features": self.n_features, "master": self.master.cpu().numpy().tolist()}
 
 
-def features(cfg, cube: torch.Tensor, hosts: np.ndarray, extended: bool = True) -> torch.Tensor:
-    """fp32 [n, F] features of the given inner IPs, computed on the device."""
+def features(cfg, cube: torch.Tensor, hosts: np.ndarray, extended: bool = True,
+             rows: bool = True) -> torch.Tensor:
+    """fp32 [n, F] features of the given inner IPs, computed on the device:
+    F = A, A + 2 (extended) or A + 4 (extended with the row-aware pair)."""
     c = cfg if isinstance(cfg, cbaa.Config) else cbaa.Config.from_dict(cfg)
-    F = c.n_arrays + (2 if extended else 0)
+    F = c.n_arrays + ((4 if rows else 2) if extended else 0)
     n = len(hosts)
     dev = cube.device
     h = torch.from_numpy(np.ascontiguousarray(hosts, dtype=np.uint32).view(np.int32)).to(dev)
@@ -58,8 +68,14 @@ def features(cfg, cube: torch.Tensor, hosts: np.ndarray, extended: bool = True) 
 
 
 def base_log(x: torch.Tensor) -> torch.Tensor:
-    """ln(1 + Thm. 2 estimate): the union-column feature (second to last)."""
+    """ln(1 + union-column count): the second-to-last feature (row-aware with
+    the full feature set, Thm. 2 with A + 2 features)."""
     return x[:, -2]
+
+
+def row_aware_count(x: torch.Tensor) -> torch.Tensor:
+    """The row-aware linear count from the full feature set."""
+    return torch.clamp(torch.expm1(x[:, -2].double()), min=0.0)
 
 
 def predict_log(model: Model, x: torch.Tensor) -> torch.Tensor:
@@ -117,14 +133,22 @@ def train(model: Model, x: torch.Tensor, target_log: torch.Tensor, epochs: int =
     return TrainLog(steps=step, epochs=epochs, final_loss=losses[-1], losses=losses)
 
 
-def stratified_rows(counts: np.ndarray, per_bin: int, rng: np.random.Generator) -> np.ndarray:
-    """Indices of up to per_bin hosts from every power-of-two cardinality bin,
-    so training is not dominated by the many single-peer hosts."""
+def stratified_rows(counts: np.ndarray, per_bin: int, rng: np.random.Generator,
+                    oversample: bool = False) -> np.ndarray:
+    """Indices of per_bin hosts from every power-of-two cardinality bin, so
+    training is not dominated by the many single-peer hosts: bins with more
+    hosts are subsampled, bins with fewer are drawn with replacement
+    (oversample) or kept whole."""
     b = np.floor(np.log2(np.maximum(counts, 1))).astype(np.int64)
     out = []
     for v in np.unique(b):
         idx = np.flatnonzero(b == v)
-        out.append(idx if idx.size <= per_bin else rng.choice(idx, per_bin, replace=False))
+        if idx.size > per_bin:
+            out.append(rng.choice(idx, per_bin, replace=False))
+        elif oversample:
+            out.append(rng.choice(idx, per_bin, replace=True))
+        else:
+            out.append(idx)
     return rng.permutation(np.concatenate(out))
 
 
@@ -135,36 +159,40 @@ def linear_count(cfg, cube: torch.Tensor, hosts: np.ndarray) -> np.ndarray:
 
 
 def compare(est_lc: np.ndarray, est_mlp: np.ndarray, truth: np.ndarray, theta: float,
+            est_row: np.ndarray | None = None,
             bins=(1, 4, 16, 64, 256, 1024, 4096, 16384, 65536, 500001)) -> dict:
-    """Error of both estimators by cardinality bin, and detection at equal FNR:
-    the learned estimator's threshold is set so its false-negative rate over
-    hosts with >= theta peers equals linear counting's at theta."""
+    """Error of the estimators by cardinality bin, and detection at equal FNR:
+    each other estimator's threshold is set so its false-negative rate over
+    hosts with >= theta peers equals linear counting's at theta (lc: the
+    paper's Thm. 2 estimate; row: the row-aware count; mlp: the network)."""
     truth = truth.astype(np.float64)
-    rel_lc = np.abs(est_lc - truth) / truth
-    rel_ml = np.abs(est_mlp - truth) / truth
+    ests = {"lc": est_lc, "mlp": est_mlp}
+    if est_row is not None:
+        ests["row"] = est_row
+    rel = {k: np.abs(v - truth) / truth for k, v in ests.items()}
     rows = []
     for lo, hi in zip(bins[:-1], bins[1:]):
         sel = (truth >= lo) & (truth < hi)
         if not sel.any():
             continue
-        rows.append({"card_lo": lo, "card_hi": hi - 1, "hosts": int(sel.sum()),
-                     "lc_mean_rel_err": float(rel_lc[sel].mean()),
-                     "mlp_mean_rel_err": float(rel_ml[sel].mean()),
-                     "lc_median_rel_err": float(np.median(rel_lc[sel])),
-                     "mlp_median_rel_err": float(np.median(rel_ml[sel]))})
+        r = {"card_lo": lo, "card_hi": hi - 1, "hosts": int(sel.sum())}
+        for k in ests:
+            r[f"{k}_mean_rel_err"] = float(rel[k][sel].mean())
+            r[f"{k}_median_rel_err"] = float(np.median(rel[k][sel]))
+        rows.append(r)
     pos = truth >= theta
     npos = max(int(pos.sum()), 1)
     fnr_lc = float(((est_lc < theta) & pos).sum()) / npos
-    fpr_lc = float(((est_lc >= theta) & ~pos).sum()) / npos
-    # smallest threshold on the learned estimate reaching the same FNR
-    sc = np.sort(est_mlp[pos])
-    k = int(math.floor(fnr_lc * npos))
-    thr = float(sc[k]) if k < sc.size else float("inf")
-    fnr_ml = float(((est_mlp < thr) & pos).sum()) / npos
-    fpr_ml = float(((est_mlp >= thr) & ~pos).sum()) / npos
-    log_mse_lc = float(np.mean((np.log1p(est_lc) - np.log1p(truth)) ** 2))
-    log_mse_ml = float(np.mean((np.log1p(est_mlp) - np.log1p(truth)) ** 2))
-    return {"bins": rows, "theta": theta, "lc": {"fnr": fnr_lc, "fpr": fpr_lc, "log_mse": log_mse_lc,
-                                                  "mean_rel_err": float(rel_lc.mean())},
-            "mlp": {"threshold": thr, "fnr": fnr_ml, "fpr": fpr_ml, "log_mse": log_mse_ml,
-                    "mean_rel_err": float(rel_ml.mean())}}
+    out = {"bins": rows, "theta": theta}
+    for k, v in ests.items():
+        if k == "lc":
+            thr = theta
+        else:   # smallest threshold reaching linear counting's FNR
+            sc = np.sort(v[pos])
+            j = int(math.floor(fnr_lc * npos))
+            thr = float(sc[j]) if j < sc.size else float("inf")
+        out[k] = {"threshold": thr, "fnr": float(((v < thr) & pos).sum()) / npos,
+                  "fpr": float(((v >= thr) & ~pos).sum()) / npos,
+                  "log_mse": float(np.mean((np.log1p(v) - np.log1p(truth)) ** 2)),
+                  "mean_rel_err": float(rel[k].mean())}
+    return out

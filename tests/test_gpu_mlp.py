@@ -124,14 +124,15 @@ def test_adam_step_matches_oracle(cb):
     assert np.array_equal(bits, M.to_bf16(_np(m.master)))
 
 
-def test_features_match_oracle(cb):
+@pytest.mark.parametrize("rows", [False, True])
+def test_features_match_oracle(cb, rows):
     from paper_1901_06207_amd import learned
     p = default_params()
-    t = tracegen.window_small(6)
+    t = tracegen.window_core_edge(6, scale=1 / 32)    # fan-in hosts: uneven rows
     cube = cb.new_cube(p)
     cb.cbaa_update(p, cube, cb.pairs_to_device(t.pairs), 0)
     hosts = np.concatenate([t.planted_ips, t.bg_ips[:3000]])
-    x = _np(learned.features(p, cube, hosts, extended=True))
+    x = _np(learned.features(p, cube, hosts, extended=True, rows=rows))
     cube_np = O.cube_of(p, t.pairs, 0)
     g = 1 << p["log2_g"]
     lz = O.host_layer_zeros(p, cube_np, hosts)
@@ -139,9 +140,14 @@ def test_features_match_oracle(cb):
     _, ones = O.column_zeros(p, cube_np)
     eps, _ = O.thresholds(p, ones, 1024.0)
     cs = np.array([O.host_columns(p, int(h))[0] for h in hosts])
-    want = M.features(lz, uz, eps[cs], g, extended=True)
-    # device log vs libm log, then rounding to fp32
+    shared = O.row_shared(p, O.row_ones(p, cube_np)) if rows else None
+    want = M.features(lz, uz, eps[cs], g, extended=True,
+                      shared=shared[cs] if rows else None)
+    assert x.shape == want.shape
+    # device log vs libm log, a parallel sum of the row mass, rounding to fp32
     assert np.allclose(x, want, rtol=2e-6, atol=1e-6)
+    if rows:
+        assert shared.min() > 0.0
 
 
 def _window_rows(cb, learned, p, seed, scale, side, per_bin, rng):
@@ -165,11 +171,11 @@ def _window_rows(cb, learned, p, seed, scale, side, per_bin, rng):
 
 
 def test_trained_network_against_linear_count(cb):
-    """Trains on two core-edge windows (both sides) and compares with the
-    paper's Thm. 2 estimate on a third, held-out window at equal
+    """Trains on core-edge windows (both sides) and compares with the paper's
+    Thm. 2 estimate and the row-aware count on a held-out window at equal
     false-negative rate. The network must lower the log-scale error overall
-    and the mean relative error below 64 peers, where bit sharing with
-    saturated columns biases the linear count upwards."""
+    and the mean relative error below 64 peers, where rows set by fan-in
+    hosts bias the linear count upwards."""
     import torch
     from paper_1901_06207_amd import learned
     p = default_params()
@@ -181,12 +187,13 @@ def test_trained_network_against_linear_count(cb):
         ts.append(torch.from_numpy(np.log1p(c).astype(np.float32)).cuda())
     X = torch.cat(xs)
     T = torch.cat(ts)
-    model = learned.Model.new(6, seed=3)
+    model = learned.Model.new(X.shape[1], seed=3)
     log = learned.train(model, X, T, epochs=20, batch=16384)
     cube, hosts, counts, xe = _window_rows(cb, learned, p, 23, 0.5, 0, None, rng)
     est_ml = learned.predict(model, xe).cpu().numpy()
     est_lc = learned.linear_count(p, cube, hosts)
-    rep = learned.compare(est_lc, est_ml, counts, 1024.0)
+    est_row = learned.row_aware_count(xe).cpu().numpy()
+    rep = learned.compare(est_lc, est_ml, counts, 1024.0, est_row=est_row)
     rep["train"] = {"rows": int(X.shape[0]), "epochs": log.epochs, "steps": log.steps,
                     "loss_by_epoch": log.losses}
     out = os.path.join(ROOT, "gpurun_out")
@@ -198,6 +205,7 @@ def test_trained_network_against_linear_count(cb):
         print(row, flush=True)
     assert log.losses[-1] < log.losses[0]
     assert rep["mlp"]["log_mse"] < rep["lc"]["log_mse"]
+    assert rep["row"]["log_mse"] < rep["lc"]["log_mse"]
     small = [r for r in rep["bins"] if r["card_hi"] < 64]
     assert sum(r["mlp_mean_rel_err"] * r["hosts"] for r in small) < \
         sum(r["lc_mean_rel_err"] * r["hosts"] for r in small)

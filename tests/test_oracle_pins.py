@@ -304,6 +304,104 @@ def test_thm2_correction_reduces_bias_under_sharing():
     assert bias_thm2 < 0.05 * n
 
 
+# ---------------------------------------------------------------- row fills
+
+def _layout(p):
+    g = 1 << p["log2_g"]
+    A = p["n_ra"] + p["n_va"]
+    ncol = [1 << p["cbn"][a] for a in range(A)]
+    return g, A, ncol, sum(ncol), [int(sum(ncol[:a])) for a in range(A)]
+
+
+def test_row_ones_by_unpacking_every_bit():
+    """Per-row counts against unpacking the whole cube bit by bit with numpy,
+    addressed by the layout formula (g = 64 and g = 128 configurations)."""
+    for name in ("default_g64", "g128_r3", "ra4_va2"):
+        p = TINY_CONFIGS[name]
+        g, A, ncol, W, aoff = _layout(p)
+        S, R = 1 << p["r"], g // 64
+        cube = O.cube_of(p, tiny_trace(9).pairs, O.SIDE_SRC)
+        bits = np.unpackbits(cube.view(np.uint8), bitorder="little").reshape(S, R, W, 64)
+        want = np.zeros((S, A, g), np.int64)
+        for a in range(A):
+            per = bits[:, :, aoff[a]:aoff[a] + ncol[a], :].sum(axis=2)   # [S, R, 64]
+            want[:, a, :] = per.reshape(S, g)
+        assert np.array_equal(O.row_ones(p, cube), want), name
+
+
+def test_row_ones_sum_to_the_array_fills():
+    """Summed over rows, the per-row counts are each array's one bits as the
+    column scan counts them."""
+    p = default_params()
+    cube = O.cube_of(p, tracegen.window_small(3).pairs, O.SIDE_SRC)
+    _, ones = O.column_zeros(p, cube)
+    assert np.array_equal(O.row_ones(p, cube).sum(axis=2).ravel(), ones.astype(np.int64))
+
+
+def test_row_shared_equals_g_eps_when_rows_fill_evenly():
+    """Every column of array a holds k_a rows in a cyclic pattern, so each row
+    is set in the same number of columns: the row-aware mass is g * eps of
+    Thm. 1 (product of fills), up to rounding."""
+    p = default_params()
+    g, A, ncol, W, aoff = _layout(p)
+    S, R = 1 << p["r"], g // 64
+    cube = np.zeros(S * R * W, np.uint64)
+    ks = [4, 16, 2, 8]
+    for a, k in enumerate(ks):
+        for col in range(ncol[a]):
+            for j in range(k):
+                b = (col * k + j) % g
+                cube[(0 * R + b // 64) * W + aoff[a] + col] |= np.uint64(1 << (b % 64))
+    rows = O.row_ones(p, cube)
+    assert np.all(rows[0] == rows[0][:, :1])          # even rows
+    shared = O.row_shared(p, rows)
+    _, ones = O.column_zeros(p, cube)
+    eps, _ = O.thresholds(p, ones, 1024.0)
+    assert shared[0] == pytest.approx(g * eps[0], rel=1e-12)
+    assert shared[0] == pytest.approx(g * np.prod([k / g for k in ks]), rel=1e-12)
+    assert np.all(shared[1:] == 0.0)
+
+
+def test_row_shared_counts_a_full_row_once():
+    """A row set in every column of every array of a sketch adds exactly 1."""
+    p = default_params()
+    g, A, ncol, W, aoff = _layout(p)
+    S, R = 1 << p["r"], g // 64
+    cube = np.zeros(S * R * W, np.uint64)
+    b0 = 777
+    cube[(2 * R + b0 // 64) * W: (2 * R + b0 // 64 + 1) * W] = np.uint64(1 << (b0 % 64))
+    shared = O.row_shared(p, O.row_ones(p, cube))
+    assert shared[2] == 1.0 and shared.sum() == 1.0
+
+
+def test_row_aware_count_removes_fan_in_row_pollution():
+    """Ten destinations with 150k distinct sources each set their row bit in
+    most source-keyed columns. Lone hosts with 5 peers then read as ~5 + the
+    polluted rows under Thm. 2; the row-aware denominator g - sum_b q_b brings
+    the estimate back to ~5."""
+    p = default_params()
+    g = 1 << p["log2_g"]
+    rng = np.random.default_rng(4)
+    srcs = rng.choice(1 << 32, 1_500_000, replace=False).astype(np.uint32)
+    dsts = rng.integers(0, 1 << 32, 10, dtype=np.uint64).astype(np.uint32)
+    fan_in = np.stack([srcs, np.repeat(dsts, 150_000)], axis=1)
+    T, n = 200, 5
+    hosts = tracegen.bijection32(np.arange(T, dtype=np.uint64) + np.uint64(5 << 24),
+                                 (3, 2654435761, 40503))
+    peers = tracegen.bijection32(np.arange(T * n, dtype=np.uint64) + np.uint64(1 << 30),
+                                 (7, 2246822519, 3266489917))
+    lone = np.stack([np.repeat(hosts, n), peers], axis=1).astype(np.uint32)
+    cube = O.cube_of(p, np.concatenate([fan_in, lone]), O.SIDE_SRC)
+    est, zeros, _ = O.estimate(p, cube, hosts)
+    shared = O.row_shared(p, O.row_ones(p, cube))
+    cs = np.array([O.host_columns(p, int(h))[0] for h in hosts])
+    row_est = -g * np.log(np.maximum(zeros, 1) / (g - shared[cs]))
+    assert shared.min() > 5.0                       # polluted rows are material
+    assert np.median(est) > n + 4.0                 # Thm. 2 overcounts them
+    assert abs(np.median(row_est) - n) < 1.0        # the row-aware count does not
+    assert abs(np.mean(row_est) - n) < 1.0
+
+
 # ---------------------------------------------------------------- restore
 
 @pytest.mark.slow
