@@ -43,11 +43,11 @@ HBM_PEAK_GBS = 8000.0
 # tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
 # valid only while the update kernels' sources are the ones measured
 # (profiles/update_core_edge_64M_traffic.txt).
-UPDATE_TRAFFIC = {"bytes": 4254335128, "sources": {
+UPDATE_TRAFFIC = {"bytes": 4003410287, "sources": {
     "paper_1901_06207_amd/csrc/cbaa_partition.hip":
-        "8f6f8847906cfe8e8e683276af87913f35d81167200cb82f03a458a710a86cc7",
+        "e02cbee4808c67dc0180d9a9469a86fde4f28d4fd451d386e3f4f6c91de8ea54",
     "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
-        "c679e14ca8c8dc96cf291fc8f2fbdea98f4db76dd8bf9cc460dfc2ed2144d551"}}
+        "4b83980cd54998815d66cfbb25a2ad4d0d19e8ed8a7fd9521361be13b07e6b2d"}}
 
 
 def measured_traffic(record, default_workload):

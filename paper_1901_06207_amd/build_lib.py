@@ -31,13 +31,17 @@ def build(verbose: bool = False) -> str:
 
     def compile_one(src: str) -> str:
         obj = os.path.join(BUILD, os.path.basename(src) + ".o")
-        cmd = ["hipcc", *FLAGS, "-c", src, "-o", obj]
+        # the per-kernel register/scratch report is kept next to the object
+        cmd = ["hipcc", *FLAGS, "-Rpass-analysis=kernel-resource-usage", "-c", src, "-o", obj]
         r = subprocess.run(cmd, capture_output=True, text=True)
         if r.returncode != 0:
             raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
+        with open(obj + ".resources.txt", "w") as f:
+            f.write("\n".join(l for l in r.stderr.splitlines() if "kernel-resource-usage" in l))
         if verbose and r.stderr.strip():
             sys.stderr.write("\n".join(l for l in r.stderr.splitlines()
-                                       if "packed-fp32-ops" not in l) + "\n")
+                                       if "packed-fp32-ops" not in l
+                                       and "kernel-resource-usage" not in l) + "\n")
         return obj
 
     with ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:

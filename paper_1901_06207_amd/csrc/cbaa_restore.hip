@@ -252,6 +252,7 @@ __device__ inline uint32_t col_zeros(const Dims& d, const Col<RPL>& c) {
 
 struct JoinArgs {
   const uint64_t* cube;
+  const uint16_t* zeros;  // [S][W] per-column zero counts of the scan
   const uint16_t* hot;
   const uint64_t* hcol;   // gathered hot columns ([S][n_ra][gcap][R])
   const uint32_t* gfit;   // [S][n_ra] list gathered
@@ -362,6 +363,16 @@ __device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t z
           uint32_t lp = 0;
 #pragma unroll
           for (int i = 0; i < NRA; ++i) lp |= rotl_in(t[i] & low_mask(d.ep[i]), d.off[i], d.L);
+          // the union column is contained in every VA column, so it has at
+          // least as many zeros: a VA column over Zmax rejects the tuple
+          // before any of its words are read
+          int32_t zva = 0;
+#pragma unroll
+          for (int v = 0; v < NVA; ++v) {
+            const int32_t zv = ja.zeros[(uint64_t)cs * d.W + d.aoff[NRA + v] + va_col(d, v, lp)];
+            zva = zv > zva ? zv : zva;
+          }
+          if (zva > zm) continue;
 #pragma unroll
           for (int v = 0; v < NVA; ++v) {
             Col<RPL> vc;
@@ -765,8 +776,8 @@ int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void
                      rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats, cube, rs.hcol, rs.gcap,
                      rs.gfit);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
-  JoinArgs ja{cube, rs.hot, rs.hcol, rs.gfit, rs.gcap, rs.hcnt, rs.zmax, rs.eps, rs.stage,
-              capacity, stats};
+  JoinArgs ja{cube, rs.zeros, rs.hot, rs.hcol, rs.gfit, rs.gcap, rs.hcnt, rs.zmax, rs.eps,
+              rs.stage, capacity, stats};
   if ((rc = run_join(d, ja, s)) != CBAA_OK) return rc;
   if (capacity == 0) return CBAA_OK;
   const uint64_t small = capacity < kSmallSort ? capacity : kSmallSort;
