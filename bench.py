@@ -227,10 +227,15 @@ def main():
     # bytes = 8 B per packet read + every router cube written once
     upd_alg_bytes = 8.0 * trace.n + 2.0 * len(parts) * cube_bytes
     achieved = upd_alg_bytes / (upd_ms.mean() * 1e-3) / 1e9
+    traffic = measured_traffic(UPDATE_TRAFFIC, len(parts) == 2 and tuning is None
+                               and args.scale == 1.0)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": measured_traffic(UPDATE_TRAFFIC, len(parts) == 2 and tuning is None
-                                            and args.scale == 1.0),
+                "traffic": traffic,
+                # the measured HBM bytes over the same duration: how close the
+                # kernels run to the memory system on the bytes they do move
+                "traffic_frac": (round(traffic / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
+                                 if traffic else None),
                 "kernel": "cbaa_update_batch (histogram, scan, scatter, apply)",
                 "per_launch": {"packets": int(trace.n), "alg_bytes": int(upd_alg_bytes),
                                "avg_ms": round(float(upd_ms.mean()), 4)}}

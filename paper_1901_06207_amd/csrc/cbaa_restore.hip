@@ -13,9 +13,8 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kPrepBlock = 1024;
 constexpr int kJoinBlock = 256;
-constexpr int kSortChunk = 4096;   // entries sorted per block in LDS
-constexpr int kSortBlock = 1024;
 constexpr uint32_t kSmallSort = 32768;   // lists up to this size are ranked all-pairs
+constexpr uint32_t kBuckets = 65536;     // larger lists: buckets by the IP's top 16 bits
 constexpr uint32_t kGatherCap = 1024;    // hot columns per (sketch, RA) list gathered
 constexpr uint64_t kGatherBytes = 256ull << 20;
 
@@ -35,7 +34,8 @@ struct RestoreScratch {
   uint32_t* rows;   // [S][A][g] columns of each array with each bit set (features)
   double* shared;   // [S] row-aware shared-bit mass (features)
   cbaa_host* stage; // [capacity]
-  uint64_t* keys;   // [capacity]
+  uint64_t* keys;   // [capacity]: index and IP of each entry, bucket-ordered
+  uint32_t* bucket; // [2][kBuckets + 1]: starts, fills
   uint64_t bytes;
 };
 
@@ -65,6 +65,7 @@ RestoreScratch carve(const Dims& d, void* base, uint64_t capacity) {
   r.shared = (double*)take((uint64_t)d.S * 8);
   r.stage = (cbaa_host*)take(capacity * sizeof(cbaa_host));
   r.keys = (uint64_t*)take(capacity * 8);
+  r.bucket = (uint32_t*)take(2ull * (kBuckets + 1) * 4);
   r.bytes = off;
   return r;
 }
@@ -440,9 +441,8 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
 
 // ---- ordering of the restored list --------------------------------------
 // Keys are (ip << 32 | stage index); restored IPs are distinct, the index
-// keeps keys unique regardless. Each block sorts kSortChunk keys in LDS
-// (bitonic); a second kernel ranks every key against the other chunks by
-// binary search and scatters the entry to its final place.
+// keeps keys unique regardless. The rank of a key is the number of smaller
+// keys, and the entry is written there.
 
 // Lists of at most kSmallSort entries: one wave per entry counts the smaller
 // keys over the whole list and writes the entry at that rank.
@@ -461,50 +461,95 @@ __global__ __launch_bounds__(256) void k_rank_small(const cbaa_host* __restrict_
   if (lane_id() == 0) out[rank] = stage[e];
 }
 
-// Larger lists: chunks sorted in LDS, then ranked across chunks.
-__global__ __launch_bounds__(kSortBlock) void k_sort_chunks(const cbaa_host* stage,
-                                                            const cbaa_restore_stats* stats,
-                                                            uint64_t capacity, uint64_t* keys) {
-  __shared__ uint64_t k[kSortChunk];
-  const uint64_t n = stats->n_hosts < capacity ? stats->n_hosts : capacity;
+// Larger lists: a counting sort into 2^16 buckets by the IP's top 16 bits,
+// then each entry is ranked inside its bucket (restored IPs are distinct; the
+// stage index breaks ties all the same). Uniform IPs leave ~n/2^16 entries per
+// bucket; one bucket never holds more than the 2^16 IPs of its /16.
+__device__ inline uint64_t list_size(const cbaa_restore_stats* stats, uint64_t capacity) {
+  return stats->n_hosts < capacity ? stats->n_hosts : capacity;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_zero(const cbaa_restore_stats* stats,
+                                                     uint64_t capacity, uint32_t* bucket) {
+  if (list_size(stats, capacity) <= kSmallSort) return;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < 2 * (kBuckets + 1); i += gridDim.x * 256)
+    bucket[i] = 0;
+}
+
+__global__ __launch_bounds__(256) void k_bucket_count(const cbaa_host* __restrict__ stage,
+                                                      const cbaa_restore_stats* stats,
+                                                      uint64_t capacity, uint32_t* cnt) {
+  const uint64_t n = list_size(stats, capacity);
   if (n <= kSmallSort) return;
-  const uint64_t base = (uint64_t)blockIdx.x * kSortChunk;
-  if (base >= n) return;
-  const uint32_t m = (uint32_t)(n - base < kSortChunk ? n - base : kSortChunk);
-  for (uint32_t i = threadIdx.x; i < m; i += kSortBlock)
-    k[i] = ((uint64_t)stage[base + i].ip << 32) | (uint32_t)(base + i);
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (uint64_t)gridDim.x * 256)
+    atomicAdd(&cnt[stage[i].ip >> 16], 1u);
+}
+
+// One block: counts -> exclusive starts in place (start[kBuckets] = n).
+__global__ __launch_bounds__(1024) void k_bucket_scan(const cbaa_restore_stats* stats,
+                                                      uint64_t capacity, uint32_t* cnt) {
+  __shared__ uint32_t wsum[1024 / kWave];
+  if (list_size(stats, capacity) <= kSmallSort) return;
+  constexpr uint32_t kPer = kBuckets / 1024;
+  uint32_t* c = cnt + threadIdx.x * kPer;
+  uint32_t mine = 0;
+  for (uint32_t i = 0; i < kPer; ++i) mine += c[i];
+  uint32_t incl = mine;   // inclusive scan over the wave, then over waves
+  for (int o = 1; o < kWave; o <<= 1) {
+    const uint32_t t = __shfl_up(incl, o, kWave);
+    if (lane_id() >= (uint32_t)o) incl += t;
+  }
+  const uint32_t wid = threadIdx.x / kWave;
+  if (lane_id() == kWave - 1) wsum[wid] = incl;
   __syncthreads();
-  // keys are distinct: the rank of a key is the number of smaller keys
-  for (uint32_t i = threadIdx.x; i < m; i += kSortBlock) {
-    const uint64_t key = k[i];
-    uint32_t rank = 0;
-    for (uint32_t j = 0; j < m; ++j) rank += k[j] < key ? 1u : 0u;
-    keys[base + rank] = key;
+  uint32_t before = 0, total = 0;
+  for (uint32_t w = 0; w < 1024 / kWave; ++w) {
+    if (w < wid) before += wsum[w];
+    total += wsum[w];
+  }
+  uint32_t run = before + incl - mine;
+  for (uint32_t i = 0; i < kPer; ++i) {
+    const uint32_t v = c[i];
+    c[i] = run;
+    run += v;
+  }
+  if (threadIdx.x == 0) cnt[kBuckets] = total;
+}
+
+// keys[pos] = (IP << 32) | stage index, grouped by bucket (order inside a
+// bucket is whatever the atomics give).
+__global__ __launch_bounds__(256) void k_bucket_scatter(const cbaa_host* __restrict__ stage,
+                                                        const cbaa_restore_stats* stats,
+                                                        uint64_t capacity,
+                                                        const uint32_t* __restrict__ start,
+                                                        uint32_t* fill, uint64_t* keys) {
+  const uint64_t n = list_size(stats, capacity);
+  if (n <= kSmallSort) return;
+  for (uint64_t i = (uint64_t)blockIdx.x * 256 + threadIdx.x; i < n;
+       i += (uint64_t)gridDim.x * 256) {
+    const uint32_t ip = stage[i].ip;
+    const uint32_t b = ip >> 16;
+    keys[start[b] + atomicAdd(&fill[b], 1u)] = ((uint64_t)ip << 32) | (uint32_t)i;
   }
 }
 
-__global__ __launch_bounds__(256) void k_rank_scatter(const cbaa_host* stage, const uint64_t* keys,
-                                                      const cbaa_restore_stats* stats,
-                                                      uint64_t capacity, cbaa_host* out) {
-  const uint64_t n = stats->n_hosts < capacity ? stats->n_hosts : capacity;
+__global__ __launch_bounds__(256) void k_bucket_rank(const cbaa_host* __restrict__ stage,
+                                                     const cbaa_restore_stats* stats,
+                                                     uint64_t capacity,
+                                                     const uint32_t* __restrict__ start,
+                                                     const uint64_t* __restrict__ keys,
+                                                     cbaa_host* out) {
+  const uint64_t n = list_size(stats, capacity);
   if (n <= kSmallSort) return;
-  const uint64_t g = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (g >= n) return;
-  const uint64_t key = keys[g];
-  const uint64_t my_chunk = g / kSortChunk;
-  uint64_t rank = g - my_chunk * kSortChunk;
-  const uint64_t nchunks = (n + kSortChunk - 1) / kSortChunk;
-  for (uint64_t c = 0; c < nchunks; ++c) {
-    if (c == my_chunk) continue;
-    uint64_t lo = c * kSortChunk;
-    uint64_t hi = lo + kSortChunk < n ? lo + kSortChunk : n;
-    while (lo < hi) {  // count keys < key in chunk c
-      const uint64_t mid = (lo + hi) / 2;
-      if (keys[mid] < key) lo = mid + 1; else hi = mid;
-    }
-    rank += lo - c * kSortChunk;
+  for (uint64_t j = (uint64_t)blockIdx.x * 256 + threadIdx.x; j < n;
+       j += (uint64_t)gridDim.x * 256) {
+    const uint64_t key = keys[j];
+    const uint32_t b = (uint32_t)(key >> 48);
+    const uint32_t lo = start[b], hi = start[b + 1];
+    uint32_t rank = 0;
+    for (uint32_t k = lo; k < hi; ++k) rank += keys[k] < key ? 1u : 0u;
+    out[lo + rank] = stage[(uint32_t)key];
   }
-  out[rank] = stage[(uint32_t)key];
 }
 
 // ---- point estimates ------------------------------------------------------
@@ -784,13 +829,20 @@ int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void
   hipLaunchKernelGGL(k_rank_small, dim3((uint32_t)((small + 3) / 4)), dim3(256), 0, s, rs.stage,
                      stats, capacity, out);
   if ((rc = check_launch("rank launch")) != CBAA_OK) return rc;
-  const uint32_t nchunks = (uint32_t)((capacity + kSortChunk - 1) / kSortChunk);
-  hipLaunchKernelGGL(k_sort_chunks, dim3(nchunks), dim3(kSortBlock), 0, s, rs.stage, stats,
-                     capacity, rs.keys);
-  if ((rc = check_launch("sort launch")) != CBAA_OK) return rc;
-  hipLaunchKernelGGL(k_rank_scatter, dim3((uint32_t)((capacity + 255) / 256)), dim3(256), 0, s,
-                     rs.stage, rs.keys, stats, capacity, out);
-  return check_launch("scatter launch");
+  // larger lists (each kernel returns at once when the list is small)
+  uint64_t gb = (capacity + 255) / 256;
+  if (gb > 8192) gb = 8192;
+  uint32_t* start = rs.bucket;
+  uint32_t* fill = rs.bucket + kBuckets + 1;
+  hipLaunchKernelGGL(k_bucket_zero, dim3(256), dim3(256), 0, s, stats, capacity, rs.bucket);
+  hipLaunchKernelGGL(k_bucket_count, dim3((uint32_t)gb), dim3(256), 0, s, rs.stage, stats, capacity,
+                     start);
+  hipLaunchKernelGGL(k_bucket_scan, dim3(1), dim3(1024), 0, s, stats, capacity, start);
+  hipLaunchKernelGGL(k_bucket_scatter, dim3((uint32_t)gb), dim3(256), 0, s, rs.stage, stats,
+                     capacity, start, fill, rs.keys);
+  hipLaunchKernelGGL(k_bucket_rank, dim3((uint32_t)gb), dim3(256), 0, s, rs.stage, stats, capacity,
+                     start, rs.keys, out);
+  return check_launch("sort launches");
 }
 
 int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
