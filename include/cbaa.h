@@ -242,6 +242,18 @@ int cbaa_restore(const cbaa_config* h_cfg, const void* d_cube, double theta, int
                  void* d_scratch, uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
                  cbaa_restore_stats* d_stats, void* stream);
 
+/* The global server's window end in one call (Sec. 3.3): d_dst = bitwise OR
+ * of the k router cubes (as cbaa_merge_or; d_dst may equal a source), then
+ * the restore of d_dst exactly as cbaa_restore. For k <= 16 the OR and the
+ * per-column zero counts the restore starts from are computed in one pass
+ * over the sources, so the merged cube is written once and never re-read
+ * for the counts; larger k merges first. Arguments and results as for
+ * cbaa_merge_or and cbaa_restore. */
+int cbaa_merge_restore(const cbaa_config* h_cfg, void* d_dst, const void* const* h_srcs, int k,
+                       double theta, int thr_rule, void* d_scratch, uint64_t scratch_bytes,
+                       cbaa_host* d_out, uint64_t capacity, cbaa_restore_stats* d_stats,
+                       void* stream);
+
 /* Thm. 2 estimate for given inner IPs: d_est[k] (double), d_zeros[k] (Z of
  * the union column) and, if d_layer_zeros is not NULL, the zero count of each
  * of the host's n_ra+n_va columns at d_layer_zeros[k*A + a] (uint16). eps is

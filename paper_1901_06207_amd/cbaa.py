@@ -145,6 +145,8 @@ def lib():
         "cbaa_column_zeros": (i32, [cfgp, vp, vp, vp, vp]),
         "cbaa_restore": (i32, [cfgp, vp, dbl, i32, vp, u64, vp, u64, vp, vp]),
         "cbaa_estimate": (i32, [cfgp, vp, vp, u64, vp, vp, vp, vp, u64, vp]),
+        "cbaa_merge_restore": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, vp, u64, vp, u64, vp,
+                                     vp]),
         "cbaa_mlp_param_count": (C.c_uint32, [C.c_uint32]),
         "cbaa_mlp_init": (i32, [C.c_uint32, C.c_uint32, i32, vp, vp, vp]),
         "cbaa_mlp_features": (i32, [cfgp, vp, vp, u64, C.c_uint32, vp, vp, u64, vp]),
@@ -320,6 +322,18 @@ def cbaa_restore(cfg, cube: torch.Tensor, theta: float, rule: int, scratch: torc
                               _dev_ptr(scratch, "scratch"), sb,
                               _dev_ptr(out, "out") if capacity else None, capacity,
                               _dev_ptr(stats, "stats"), _stream(stream)), "cbaa_restore")
+
+
+def cbaa_merge_restore(cfg, dst: torch.Tensor, srcs: Sequence[torch.Tensor], theta: float,
+                       rule: int, scratch: torch.Tensor, out: Optional[torch.Tensor],
+                       capacity: int, stats: torch.Tensor, stream=None) -> None:
+    arr = (C.c_void_p * len(srcs))(*[_dev_ptr(x, "src") for x in srcs])
+    sb = scratch.numel() * scratch.element_size()
+    _check(lib().cbaa_merge_restore(C.byref(_cfg(cfg)), _dev_ptr(dst, "dst"), arr, len(srcs),
+                                    float(theta), rule, _dev_ptr(scratch, "scratch"), sb,
+                                    _dev_ptr(out, "out") if capacity else None, capacity,
+                                    _dev_ptr(stats, "stats"), _stream(stream)),
+           "cbaa_merge_restore")
 
 
 def cbaa_estimate(cfg, cube: torch.Tensor, hosts: torch.Tensor, est: torch.Tensor,

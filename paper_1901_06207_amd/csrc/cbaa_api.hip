@@ -301,6 +301,32 @@ int cbaa_restore(const cbaa_config* cfg, const void* d_cube, double theta, int t
                         d_stats, (hipStream_t)stream);
 }
 
+int cbaa_merge_restore(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
+                       double theta, int thr_rule, void* d_scratch, uint64_t scratch_bytes,
+                       cbaa_host* d_out, uint64_t capacity, cbaa_restore_stats* d_stats,
+                       void* stream) {
+  CHECK_DIMS(cfg, d);
+  REQUIRE(d_dst && ((uintptr_t)d_dst & 15u) == 0, "destination must be 16-byte aligned");
+  REQUIRE(h_srcs && k >= 1, "need at least one source cube");
+  for (int i = 0; i < k; ++i)
+    REQUIRE(h_srcs[i] && ((uintptr_t)h_srcs[i] & 15u) == 0, "source %d null or not 16-byte aligned", i);
+  REQUIRE(thr_rule == CBAA_THR_THM2 || thr_rule == CBAA_THR_PAPER, "unknown threshold rule");
+  REQUIRE(theta >= 0.0 && isfinite(theta), "theta must be finite and non-negative");
+  REQUIRE(d_stats, "null stats");
+  REQUIRE(capacity == 0 || d_out, "null output with non-zero capacity");
+  REQUIRE(capacity < (1ull << 32), "capacity must be below 2^32");
+  REQUIRE(d_scratch && ((uintptr_t)d_scratch & 255u) == 0, "scratch must be 256-byte aligned");
+  if (scratch_bytes < restore_scratch_bytes(d, capacity)) {
+    set_error("restore scratch of %llu bytes is below the required %llu",
+              (unsigned long long)scratch_bytes,
+              (unsigned long long)restore_scratch_bytes(d, capacity));
+    return CBAA_ESCRATCH;
+  }
+  const double x = exp(-theta / (double)d.g);
+  return launch_merge_restore(d, (uint64_t*)d_dst, (const uint64_t* const*)h_srcs, k, x, thr_rule,
+                              d_scratch, capacity, d_out, d_stats, (hipStream_t)stream);
+}
+
 int cbaa_estimate(const cbaa_config* cfg, const void* d_cube, const uint32_t* d_hosts, uint64_t n,
                   double* d_est, uint16_t* d_zeros, uint16_t* d_layer_zeros, void* d_scratch,
                   uint64_t scratch_bytes, void* stream) {

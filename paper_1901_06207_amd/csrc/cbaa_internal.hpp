@@ -139,6 +139,9 @@ int launch_column_zeros(const Dims& d, const uint64_t* cube, uint16_t* zeros, ui
 uint64_t restore_scratch_bytes(const Dims& d, uint64_t capacity);
 int launch_restore(const Dims& d, const uint64_t* cube, double x_theta, int rule, void* scratch,
                    uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s);
+int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
+                         double x_theta, int rule, void* scratch, uint64_t capacity,
+                         cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s);
 int launch_features(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
                     uint32_t F, float* x, void* scratch, hipStream_t s);
 int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,

@@ -124,6 +124,63 @@ __global__ __launch_bounds__(kScanBlock) void k_column_zeros(Dims d, const uint4
     atomicAdd(&ones[cs * d.A + threadIdx.x], part[threadIdx.x]);
 }
 
+// The global server's OR-merge and the column scan in one pass: the same
+// walk as k_column_zeros, each 16-byte unit being the OR of up to 16 source
+// cubes, stored to dst and then counted. dst may be one of the sources: every
+// unit is read from all sources by the thread that writes it.
+constexpr int kMergeScanSources = 16;
+
+struct MergeSrc {
+  const uint4* p[kMergeScanSources];
+};
+
+__global__ __launch_bounds__(kScanBlock) void k_merge_scan(Dims d, MergeSrc src, int k, uint4* dst,
+                                                           uint32_t* __restrict__ zeros2,
+                                                           uint32_t* __restrict__ ones) {
+  __shared__ uint32_t part[CBAA_MAX_ARRAYS];
+  const uint32_t cs = blockIdx.y;
+  if (threadIdx.x < CBAA_MAX_ARRAYS) part[threadIdx.x] = 0;
+  __syncthreads();
+  const uint32_t pair = blockIdx.x * kScanBlock + threadIdx.x;  // column pair index
+  const uint32_t half_w = d.W / 2;
+  if (pair < half_w) {
+    uint32_t c0 = 0, c1 = 0;
+    const uint64_t first = ((uint64_t)cs * d.R) * half_w + pair;
+    constexpr uint32_t kU = 8;
+    for (uint32_t rb0 = 0; rb0 < d.R; rb0 += kU) {
+      uint4 v[kU];
+#pragma unroll
+      for (uint32_t u = 0; u < kU; ++u) v[u] = make_uint4(0u, 0u, 0u, 0u);
+      for (int j = 0; j < k; ++j) {
+#pragma unroll
+        for (uint32_t u = 0; u < kU; ++u) {
+          if (rb0 + u >= d.R) break;
+          const uint4 w = src.p[j][first + (uint64_t)(rb0 + u) * half_w];
+          v[u].x |= w.x;
+          v[u].y |= w.y;
+          v[u].z |= w.z;
+          v[u].w |= w.w;
+        }
+      }
+#pragma unroll
+      for (uint32_t u = 0; u < kU; ++u) {
+        if (rb0 + u >= d.R) break;
+        dst[first + (uint64_t)(rb0 + u) * half_w] = v[u];
+        c0 += __popc(v[u].x) + __popc(v[u].y);
+        c1 += __popc(v[u].z) + __popc(v[u].w);
+      }
+    }
+    zeros2[(uint64_t)cs * half_w + pair] = (d.g - c0) | ((d.g - c1) << 16);
+    const uint32_t w = 2 * pair;
+    uint32_t a = 0;
+    while (a + 1 < d.A && w >= d.aoff[a + 1]) ++a;
+    atomicAdd(&part[a], c0 + c1);
+  }
+  __syncthreads();
+  if (threadIdx.x < d.A && part[threadIdx.x])
+    atomicAdd(&ones[cs * d.A + threadIdx.x], part[threadIdx.x]);
+}
+
 // Per-sketch eps (Thm. 1 with the measured fills) and Zmax, in fp64 with the
 // operations in the order the oracle uses.
 __device__ inline int32_t sketch_threshold(const Dims& d, const uint32_t* ones, uint32_t cs,
@@ -812,11 +869,14 @@ int launch_column_zeros(const Dims& d, const uint64_t* cube, uint16_t* zeros, ui
   return run_scan(d, cube, zeros, ones, nullptr, s);
 }
 
-int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void* scratch,
-                   uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s) {
-  RestoreScratch rs = carve(d, scratch, capacity);
-  int rc = run_scan(d, cube, rs.zeros, rs.ones, stats, s);
-  if (rc != CBAA_OK) return rc;
+namespace {
+
+// Everything after the column scan: thresholds, hot lists and gather, join,
+// ordering.
+int restore_after_scan(const Dims& d, const uint64_t* cube, double x, int rule,
+                       const RestoreScratch& rs, uint64_t capacity, cbaa_host* out,
+                       cbaa_restore_stats* stats, hipStream_t s) {
+  int rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, d.n_ra), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
                      rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats, cube, rs.hcol, rs.gcap,
                      rs.gfit);
@@ -843,6 +903,38 @@ int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void
   hipLaunchKernelGGL(k_bucket_rank, dim3((uint32_t)gb), dim3(256), 0, s, rs.stage, stats, capacity,
                      start, rs.keys, out);
   return check_launch("sort launches");
+}
+
+}  // namespace
+
+int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void* scratch,
+                   uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s) {
+  RestoreScratch rs = carve(d, scratch, capacity);
+  int rc = run_scan(d, cube, rs.zeros, rs.ones, stats, s);
+  if (rc != CBAA_OK) return rc;
+  return restore_after_scan(d, cube, x, rule, rs, capacity, out, stats, s);
+}
+
+int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
+                         double x, int rule, void* scratch, uint64_t capacity, cbaa_host* out,
+                         cbaa_restore_stats* stats, hipStream_t s) {
+  if (k > kMergeScanSources) {   // merge in passes first, then the plain restore
+    const int rc = launch_merge_or(d, dst, srcs, k, s);
+    if (rc != CBAA_OK) return rc;
+    return launch_restore(d, dst, x, rule, scratch, capacity, out, stats, s);
+  }
+  RestoreScratch rs = carve(d, scratch, capacity);
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, stats, rs.ones, d.S * d.A);
+  int rc = check_launch("reset launch");
+  if (rc != CBAA_OK) return rc;
+  MergeSrc ms{};
+  for (int j = 0; j < k; ++j) ms.p[j] = (const uint4*)srcs[j];
+  const uint32_t half_w = d.W / 2;
+  dim3 grid((half_w + kScanBlock - 1) / kScanBlock, d.S);
+  hipLaunchKernelGGL(k_merge_scan, grid, dim3(kScanBlock), 0, s, d, ms, k, (uint4*)dst,
+                     (uint32_t*)rs.zeros, rs.ones);
+  if ((rc = check_launch("merge scan launch")) != CBAA_OK) return rc;
+  return restore_after_scan(d, dst, x, rule, rs, capacity, out, stats, s);
 }
 
 int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,

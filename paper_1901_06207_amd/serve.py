@@ -226,14 +226,11 @@ class Server:
         torch.cuda.synchronize(self.dev)
         t0 = time.perf_counter()
         s = torch.cuda.current_stream(self.dev)
-        cbaa.cbaa_merge_or(self.cfg, self.g_src, [c[0] for c in self.cubes], s)
-        cubes = [self.g_src]
-        if self.both:
-            cbaa.cbaa_merge_or(self.cfg, self.g_dst, [c[1] for c in self.cubes], s)
-            cubes.append(self.g_dst)
-        for i, g in enumerate(cubes):
-            cbaa.cbaa_restore(self.cfg, g, self.theta, cbaa.THR_THM2, self.rs[i], self.outs[i],
-                              self.capacity, self.stats[i], s)
+        cubes = [self.g_src] + ([self.g_dst] if self.both else [])
+        for i, g in enumerate(cubes):   # per side: OR-merge and restore in one call
+            cbaa.cbaa_merge_restore(self.cfg, g, [c[i] for c in self.cubes], self.theta,
+                                    cbaa.THR_THM2, self.rs[i], self.outs[i], self.capacity,
+                                    self.stats[i], s)
         for a, b in self.cubes if reset else []:
             cbaa.cbaa_cube_init(self.cfg, a, s)
             if b is not None:

@@ -324,6 +324,37 @@ def test_restore_tens_of_thousands_of_hosts(cb):
     assert np.all(np.diff(got["ip"].astype(np.int64)) > 0)
 
 
+@pytest.mark.parametrize("k,alias", [(1, False), (2, False), (3, True), (16, False), (17, True)])
+def test_merge_restore_equals_merge_then_restore(cb, k, alias):
+    """The fused window end (OR-merge counted in one pass, then the restore)
+    gives the cube and the host list of cbaa_merge_or followed by
+    cbaa_restore, for k routers (k > 16 takes the merge-first path), with the
+    destination one of the sources or not; and the oracle's hosts."""
+    import torch
+    p = default_params()
+    t = tracegen.window_small(7)
+    parts = tracegen.split_routers(t.pairs, k, seed=7)
+    srcs = [_gpu_cube(cb, p, q, 0) for q in parts]
+    dst = srcs[0] if alias else cb.new_cube(p, init=False)
+    want_cube = O.cube_of(p, t.pairs, 0)
+    cap = 4096
+    rs = cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, cap))
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    st = cb.stats_tensor()
+    _say("merge restore", k, alias)
+    cb.cbaa_merge_restore(p, dst, srcs, 1024.0, cb.THR_THM2, rs, out, cap, st)
+    torch.cuda.synchronize()
+    assert np.array_equal(cb.cube_to_numpy(dst), want_cube)
+    got = cb.host_list(out, int(st[0]))
+    want, _ = O.restore(p, want_cube, 1024.0)
+    _assert_hosts_equal(got, want)
+    # the same window through the two separate calls
+    g2 = cb.new_cube(p, init=False)
+    cb.cbaa_merge_or(p, g2, [s_ for s_ in srcs if s_ is not dst] + ([dst] if alias else []))
+    got2, _ = cb.restore(p, g2, 1024.0)
+    _assert_hosts_equal(got2, got)
+
+
 # ---------------------------------------------------------------- estimate
 
 def test_estimate_matches_oracle(cb):
