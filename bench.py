@@ -43,11 +43,11 @@ HBM_PEAK_GBS = 8000.0
 # tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
 # valid only while the update kernels' sources are the ones measured
 # (profiles/update_core_edge_64M_traffic.txt).
-UPDATE_TRAFFIC = {"bytes": 4003410287, "sources": {
+UPDATE_TRAFFIC = {"bytes": 4011574750, "sources": {
     "paper_1901_06207_amd/csrc/cbaa_partition.hip":
         "e02cbee4808c67dc0180d9a9469a86fde4f28d4fd451d386e3f4f6c91de8ea54",
     "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
-        "4b83980cd54998815d66cfbb25a2ad4d0d19e8ed8a7fd9521361be13b07e6b2d"}}
+        "84680ce1736e72de2064e9eeec6e3166ce2dac8f9f0a71f0de6cf8e23126c5cb"}}
 
 
 def measured_traffic(record, default_workload):

@@ -889,7 +889,9 @@ int restore_after_scan(const Dims& d, const uint64_t* cube, double x, int rule,
   hipLaunchKernelGGL(k_rank_small, dim3((uint32_t)((small + 3) / 4)), dim3(256), 0, s, rs.stage,
                      stats, capacity, out);
   if ((rc = check_launch("rank launch")) != CBAA_OK) return rc;
-  // larger lists (each kernel returns at once when the list is small)
+  // larger lists (each kernel returns at once when the list is small; none
+  // is launched when the capacity itself is small)
+  if (capacity <= kSmallSort) return CBAA_OK;
   uint64_t gb = (capacity + 255) / 256;
   if (gb > 8192) gb = 8192;
   uint32_t* start = rs.bucket;
