@@ -1,6 +1,6 @@
 /*
  * cbaa_mlp.h -- learned cardinality estimator of libcbaa (an extension of the
- * paper's method, judged against it).
+ * paper's method, compared against it).
  *
  * The paper estimates a restored host's cardinality from the zero bits of its
  * union column with the eps-corrected linear count of Thm. 2 (from Eq. 1).

@@ -4,7 +4,7 @@ A plain numpy fp64 reference of the small network that maps a host's
 per-array ("per-layer") column popcounts to a corrected cardinality
 estimate, its mean-squared-error gradient and one Adam step. The paper's own
 estimator is Thm. 2's corrected linear count; this network is an addition
-that is judged against it.
+that is compared against it.
 
 Network (F inputs, two hidden layers of 64, one output):
     z1 = W1 x + b1,  h1 = relu(z1)

@@ -123,7 +123,8 @@ def lib():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise ImportError(f"libcbaa.so not built at {LIB_PATH}: run __graft_entry__.build()")
+        raise ImportError(f"libcbaa.so not built at {LIB_PATH}: run "
+                          "python -m paper_1901_06207_amd.build_lib")
     L = C.CDLL(LIB_PATH)
     cfgp = C.POINTER(cbaa_config)
     vp, u64, i32, dbl = C.c_void_p, C.c_uint64, C.c_int, C.c_double

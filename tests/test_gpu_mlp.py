@@ -9,14 +9,13 @@ sides); Adam's master within 1e-6 relative plus 1e-9; the bf16 copy is
 exactly the round-to-nearest-even of the device master."""
 
 import json
-import os
 
 import numpy as np
 import pytest
 
 import oracle as O
 import tracegen
-from conftest import ROOT, default_params
+from conftest import default_params
 from oracle import mlp as M
 
 pytestmark = pytest.mark.gpu
@@ -196,10 +195,6 @@ def test_trained_network_against_linear_count(cb):
     rep = learned.compare(est_lc, est_ml, counts, 1024.0, est_row=est_row)
     rep["train"] = {"rows": int(X.shape[0]), "epochs": log.epochs, "steps": log.steps,
                     "loss_by_epoch": log.losses}
-    out = os.path.join(ROOT, "gpurun_out")
-    os.makedirs(out, exist_ok=True)
-    with open(os.path.join(out, "learned_vs_linear.json"), "w") as f:
-        json.dump(rep, f, indent=1)
     print(json.dumps({k: v for k, v in rep.items() if k != "bins"}), flush=True)
     for row in rep["bins"]:
         print(row, flush=True)
