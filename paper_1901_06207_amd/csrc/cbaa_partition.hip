@@ -21,7 +21,8 @@
 //                  stage the records bin-sorted and write every run
 //                  contiguously. The order of runs inside a bin is whatever
 //                  the atomics give: the OR of the bits does not depend on it
-//   5. apply       persistent blocks walk (stream, bin, segment) items: zero
+//   5. apply       persistent blocks take (stream, bin, segment) items from a
+//                  shared counter (work stealing across streams): zero
 //                  an LDS tile, OR the records' bits into it, flush non-zero
 //                  words to the stream's cube with atomic ORs -- or, for a
 //                  stream whose cubes start empty and a bin with one item,
@@ -75,6 +76,7 @@ struct Batch {
 
 struct Layout {
   uint32_t* tot;      // [k][nbins] records per bin (summed by the histogram)
+  uint32_t* next;     // [1] next apply item to take (right after tot)
   uint32_t* cursor;   // [k][nbins] next free record of each bin (scatter)
   uint32_t* base;     // [k][nbins + 1] record offsets inside the stream
   uint32_t* segpre;   // [k][nbins + 1] apply items inside the stream
@@ -120,7 +122,8 @@ Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
     off += align256(bytes);
     return (void*)q;
   };
-  L.tot = (uint32_t*)take((uint64_t)b.k * b.nbins * 4);
+  L.tot = (uint32_t*)take(((uint64_t)b.k * b.nbins + 1) * 4);
+  L.next = L.tot + (uint64_t)b.k * b.nbins;
   L.cursor = (uint32_t*)take((uint64_t)b.k * b.nbins * 4);
   L.base = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
   L.segpre = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
@@ -412,12 +415,20 @@ template <int NRA, int NVA>
 __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* __restrict__ rec_all,
                                                   const uint32_t* __restrict__ base,
                                                   const uint32_t* __restrict__ segpre,
-                                                  const uint32_t* __restrict__ items) {
+                                                  const uint32_t* __restrict__ items,
+                                                  uint32_t* next) {
   __shared__ __align__(16) uint64_t tile[kMaxTileWords];
+  __shared__ uint32_t s_item;
   uint32_t* tile32 = (uint32_t*)tile;
   const uint32_t n_items = items[b.k];
   const uint32_t per_cube = d.S * d.R;
-  for (uint32_t item = blockIdx.x; item < n_items; item += gridDim.x) {
+  for (;;) {
+    // every thread has read the previous item (the body ends with a barrier)
+    if (threadIdx.x == 0)
+      s_item = __hip_atomic_fetch_add(next, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    __syncthreads();
+    const uint32_t item = s_item;
+    if (item >= n_items) break;
     const uint32_t si = upper_index(items, b.k, item);
     const StreamDesc& st = b.s[si];
     const uint32_t* bs = base + (uint64_t)si * (b.nbins + 1);
@@ -483,7 +494,7 @@ int check(const char* what) {
 template <int NRA, int NVA>
 int apply_dispatch(const Dims& d, const Batch& b, const Layout& L, uint32_t blocks, hipStream_t s) {
   hipLaunchKernelGGL((k_apply<NRA, NVA>), dim3(blocks), dim3(kBlock), 0, s, d, b, L.rec, L.base,
-                     L.segpre, L.items);
+                     L.segpre, L.items, L.next);
   return check("apply launch");
 }
 
@@ -510,7 +521,7 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
     }
     return CBAA_OK;
   }
-  const uint32_t nt = b.k * b.nbins;
+  const uint32_t nt = b.k * b.nbins + 1;   // bin totals and the apply's item counter
   hipLaunchKernelGGL(k_zero_words, dim3((nt + 255) / 256), dim3(256), 0, s, L.tot, nt);
   if ((rc = check("zero launch")) != CBAA_OK) return rc;
   hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.tot);
