@@ -14,8 +14,8 @@
 //                  bin's records are contiguous) and of apply segments; the
 //                  bins' write cursors start at their bases
 //   3. items       apply items prefixed over streams
-//   4. scatter     persistent blocks take scatter chunks (kept in registers)
-//                  in an order that gives each XCD a contiguous range; per
+//   4. scatter     persistent blocks (one per CU) take scatter chunks, kept in
+//                  registers, from a shared counter; per
 //                  cube, rank the chunk's records inside their bins in LDS,
 //                  reserve each bin's run with one atomic add on its cursor,
 //                  stage the records bin-sorted and write every run
@@ -44,7 +44,7 @@ constexpr int kApplyUnroll = 16;
 constexpr uint32_t kMaxTileWords = 16384; // 128 KiB LDS tile
 constexpr int kScatterPer = 12;           // pairs per thread in a scatter chunk
 constexpr uint32_t kScatterChunk = kScatterPer * kBlock;
-constexpr uint32_t kScatterBlocks = 1024; // persistent scatter grid (4 per CU)
+constexpr uint32_t kScatterBlocks = 256;  // persistent scatter grid (one per CU)
 constexpr uint32_t kDefaultChunk = 65536;
 constexpr uint32_t kDefaultSeg = 65536;
 constexpr uint32_t kDefaultApplyBlocks = 512;
@@ -76,7 +76,7 @@ struct Batch {
 
 struct Layout {
   uint32_t* tot;      // [k][nbins] records per bin (summed by the histogram)
-  uint32_t* next;     // [1] next apply item to take (right after tot)
+  uint32_t* next;     // [2] next apply item, next scatter chunk (right after tot)
   uint32_t* cursor;   // [k][nbins] next free record of each bin (scatter)
   uint32_t* base;     // [k][nbins + 1] record offsets inside the stream
   uint32_t* segpre;   // [k][nbins + 1] apply items inside the stream
@@ -122,7 +122,7 @@ Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
     off += align256(bytes);
     return (void*)q;
   };
-  L.tot = (uint32_t*)take(((uint64_t)b.k * b.nbins + 1) * 4);
+  L.tot = (uint32_t*)take(((uint64_t)b.k * b.nbins + 2) * 4);
   L.next = L.tot + (uint64_t)b.k * b.nbins;
   L.cursor = (uint32_t*)take((uint64_t)b.k * b.nbins * 4);
   L.base = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
@@ -281,15 +281,6 @@ __global__ void k_stream_items(Batch b, const uint32_t* segpre, uint32_t* items)
   items[b.k] = acc;
 }
 
-// Block x of a grid of G blocks -> virtual block. Consecutive block ids go to
-// different XCDs (round robin over 8); this gives XCD x the contiguous range
-// of virtual blocks [x*q + min(x, r), ...), so neighbouring chunks -- whose
-// runs share cache lines at bin boundaries -- are written through one L2.
-__device__ inline uint32_t xcd_major(uint32_t x, uint32_t G) {
-  const uint32_t q = G / 8, r = G % 8, xcd = x % 8, j = x / 8;
-  return xcd * q + (xcd < r ? xcd : r) + j;
-}
-
 __device__ inline uint32_t pack_rank(uint32_t rk, int u, uint32_t rank) {
   return rk | (rank << (16 * (u & 1)));
 }
@@ -298,7 +289,8 @@ __device__ inline uint32_t unpack_rank(uint32_t rk, int u) { return (rk >> (16 *
 
 template <bool TWO>
 __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* cursor,
-                                                    uint2* __restrict__ rec_all) {
+                                                    uint2* __restrict__ rec_all, uint32_t* ctr) {
+  __shared__ uint32_t s_next;
   constexpr int kPer = kScatterPer;
   constexpr uint32_t P = kScatterChunk;
   __shared__ uint2 stage[P];
@@ -307,7 +299,6 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* c
   __shared__ uint32_t gpos[kMaxBins / 2];
   __shared__ uint32_t waves[kBlock / kWave];
   const uint32_t per_cube = d.S * d.R;   // bins of one cube (<= 1024)
-  const uint32_t G = gridDim.x;
   uint2 p[kPer];
   auto load = [&](uint32_t gc) {
     const StreamDesc& st = b.s[owner_of_schunk(b, gc)];
@@ -320,9 +311,16 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* c
       p[u] = k < rem ? src[k] : make_uint2(0u, 0u);
     }
   };
-  const uint32_t first = xcd_major(blockIdx.x, G);
-  if (first < b.total_schunks) load(first);
-  for (uint32_t gc = first; gc < b.total_schunks; gc += G) {
+  // chunks are taken from a shared counter (work stealing); the next one is
+  // claimed at the top of each chunk and loaded while the current chunk's
+  // runs are written
+  if (threadIdx.x == 0) s_next = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  __syncthreads();
+  uint32_t gc_cur = s_next;
+  __syncthreads();
+  if (gc_cur < b.total_schunks) load(gc_cur);
+  for (uint32_t gc = gc_cur; gc < b.total_schunks; gc = gc_cur) {
+    if (threadIdx.x == 0) s_next = __hip_atomic_fetch_add(ctr, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     const uint32_t si = owner_of_schunk(b, gc);
     const StreamDesc& st = b.s[si];
     uint2* rec = rec_all + st.rec_base;
@@ -373,7 +371,10 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* c
       __syncthreads();
       // the chunk's pairs are no longer needed: fetch the next chunk while
       // the runs are written
-      if (k == (TWO ? 1 : 0) && gc + G < b.total_schunks) load(gc + G);
+      if (k == (TWO ? 1 : 0)) {
+        gc_cur = s_next;
+        if (gc_cur < b.total_schunks) load(gc_cur);
+      }
       for (uint32_t t = threadIdx.x; t < total; t += kBlock) {
         const uint2 v = stage[t];
         const uint32_t bl = bin_of_record(d, v) - k * per_cube;
@@ -521,7 +522,7 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
     }
     return CBAA_OK;
   }
-  const uint32_t nt = b.k * b.nbins + 1;   // bin totals and the apply's item counter
+  const uint32_t nt = b.k * b.nbins + 2;   // bin totals, the apply's and the scatter's counters
   hipLaunchKernelGGL(k_zero_words, dim3((nt + 255) / 256), dim3(256), 0, s, L.tot, nt);
   if ((rc = check("zero launch")) != CBAA_OK) return rc;
   hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.tot);
@@ -535,7 +536,7 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
     if ((rc = check("clear launch")) != CBAA_OK) return rc;
   }
   const uint32_t sgrid = b.total_schunks < kScatterBlocks ? b.total_schunks : kScatterBlocks;
-  hipLaunchKernelGGL((k_scatter<TWO>), dim3(sgrid), dim3(kBlock), 0, s, d, b, L.cursor, L.rec);
+  hipLaunchKernelGGL((k_scatter<TWO>), dim3(sgrid), dim3(kBlock), 0, s, d, b, L.cursor, L.rec, L.next + 1);
   if ((rc = check("scatter launch")) != CBAA_OK) return rc;
   return run_apply(d, b, L, apply_blocks, s);
 }
