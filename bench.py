@@ -43,9 +43,9 @@ HBM_PEAK_GBS = 8000.0
 # tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
 # valid only while the update kernels' sources are the ones measured
 # (profiles/update_core_edge_64M_traffic.txt).
-UPDATE_TRAFFIC = {"bytes": 4003333717, "sources": {
+UPDATE_TRAFFIC = {"bytes": 4047753478, "sources": {
     "paper_1901_06207_amd/csrc/cbaa_partition.hip":
-        "59bd560de319d1306bf808be70ff9a4f682c95af732a9b54193297f68bb9a2d4",
+        "cdb6598fcf7d5dc52bbe9fc10881a540339c4a818082b21ec0e80bb94eedd4e0",
     "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
         "84680ce1736e72de2064e9eeec6e3166ce2dac8f9f0a71f0de6cf8e23126c5cb"}}
 
