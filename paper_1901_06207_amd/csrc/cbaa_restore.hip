@@ -13,6 +13,7 @@ namespace {
 constexpr int kScanBlock = 256;
 constexpr int kPrepBlock = 1024;
 constexpr int kJoinBlock = 256;
+constexpr uint32_t kJoinWaves = 2048;    // join grid: 8 waves per CU on 256 CUs
 constexpr uint32_t kSmallSort = 32768;   // lists up to this size are ranked all-pairs
 constexpr uint32_t kBuckets = 65536;     // larger lists: buckets by the IP's top 16 bits
 constexpr uint32_t kGatherCap = 1024;    // hot columns per (sketch, RA) list gathered
@@ -34,6 +35,8 @@ struct RestoreScratch {
   uint32_t* rows;   // [S][A][g] columns of each array with each bit set (features)
   double* shared;   // [S] row-aware shared-bit mass (features)
   cbaa_host* stage; // [capacity]
+  cbaa_host* wbuf;  // [kJoinWaves][kWave]: hosts each join wave found, by wave
+  uint32_t* wcnt;   // [kJoinWaves]: how many of its slots each wave filled
   uint64_t* keys;   // [capacity]: index and IP of each entry, bucket-ordered
   uint32_t* bucket; // [2][kBuckets + 1]: starts, fills
   uint64_t bytes;
@@ -64,16 +67,27 @@ RestoreScratch carve(const Dims& d, void* base, uint64_t capacity) {
   r.rows = (uint32_t*)take((uint64_t)d.S * d.A * d.g * 4);
   r.shared = (double*)take((uint64_t)d.S * 8);
   r.stage = (cbaa_host*)take(capacity * sizeof(cbaa_host));
+  r.wbuf = (cbaa_host*)take((uint64_t)kJoinWaves * kWave * sizeof(cbaa_host));
+  r.wcnt = (uint32_t*)take((uint64_t)kJoinWaves * 4);
   r.keys = (uint64_t*)take(capacity * 8);
   r.bucket = (uint32_t*)take(2ull * (kBuckets + 1) * 4);
   r.bytes = off;
   return r;
 }
 
+// Sum over the wave with DPP row shifts: after shifts by 1, 2, 4 and 8 lanes
+// inside each row of 16, the last lane of a row holds the row's total (lanes
+// whose source falls outside the row add 0); the four totals are read back as
+// wave-uniform values. The result is the same in every lane.
 __device__ inline uint32_t wave_sum(uint32_t v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-  return v;
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, 15) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 31) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 47) +
+         (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
 }
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
@@ -198,12 +212,15 @@ __device__ inline int32_t sketch_threshold(const Dims& d, const uint32_t* ones, 
   return zf < 0.0 ? -1 : (int32_t)floor(zf);
 }
 
-// Block (cs, i): Zmax of sketch cs and the ascending hot-column list of RA i
-// (Alg. 2) by ordered ballot compaction. Block (cs, 0) also stores eps, Zmax.
-// A list of at most gcap columns is then copied column by column (R words
-// strided by W in the cube) into a contiguous run of hcol, where the tuple
-// join finds every hot column of the list in 512 B at the paper's g; gfit
-// records whether it was.
+// Block (cs, i, part): Zmax of sketch cs and the ascending hot-column list of
+// RA i (Alg. 2) by ordered ballot compaction; every part builds the list, part
+// 0 stores it (and block (cs, 0, 0) stores eps, Zmax). A list of at most gcap
+// columns is then copied column by column (R words strided by W in the cube)
+// into a contiguous run of hcol, where the tuple join finds every hot column
+// of the list in 512 B at the paper's g; gfit records whether it was. The
+// copy is split over the parts, row block by row block, so that neighbouring
+// threads read neighbouring hot columns of one row block.
+constexpr uint32_t kPrepParts = 4;
 __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* __restrict__ zeros,
                                                         const uint32_t* __restrict__ ones,
                                                         double* eps, int32_t* zmax, uint32_t* hcnt,
@@ -213,11 +230,13 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
                                                         uint64_t* hcol, uint32_t gcap,
                                                         uint32_t* gfit) {
   __shared__ uint32_t wave_cnt[kPrepBlock / kWave];
+  __shared__ uint16_t s_list[kGatherCap];
   const uint32_t cs = blockIdx.x;
   const uint32_t i = blockIdx.y;
+  const bool lead = blockIdx.z == 0;
   double e;
   const int32_t zm = sketch_threshold(d, ones, cs, x, rule, &e);
-  if (i == 0 && threadIdx.x == 0) {
+  if (lead && i == 0 && threadIdx.x == 0) {
     eps[cs] = e;
     zmax[cs] = zm;
   }
@@ -239,11 +258,15 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
       if (w < wid) woff += wave_cnt[w];
       total += wave_cnt[w];
     }
-    if (pred) out[base + woff + before] = (uint16_t)j;
+    const uint32_t at = base + woff + before;
+    if (pred) {
+      if (lead) out[at] = (uint16_t)j;
+      if (at < kGatherCap) s_list[at] = (uint16_t)j;
+    }
     base += total;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
+  if (lead && threadIdx.x == 0) {
     hcnt[cs * d.n_ra + i] = base;
     if (stats)
       __hip_atomic_fetch_add(&stats->hot_columns, (uint64_t)base, __ATOMIC_RELAXED,
@@ -251,14 +274,31 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
   }
   if (!hcol) return;
   const bool fit = base <= gcap;   // base is the same in every thread
-  if (threadIdx.x == 0) gfit[cs * d.n_ra + i] = fit ? 1u : 0u;
+  if (lead && threadIdx.x == 0) gfit[cs * d.n_ra + i] = fit ? 1u : 0u;
   if (!fit) return;
-  // the list in `out` was written by this block before the last barrier
+  // s_list was written before the last barrier; gcap <= kGatherCap
   const uint64_t* src = cube + (uint64_t)cs * d.R * d.W + d.aoff[i];
   uint64_t* dst = hcol + ((uint64_t)cs * d.n_ra + i) * gcap * d.R;
-  for (uint32_t j = threadIdx.x; j < base * d.R; j += blockDim.x) {
-    const uint32_t pos = j / d.R, rb = j - pos * d.R;
-    dst[j] = src[(uint64_t)rb * d.W + out[pos]];
+  const uint32_t n = base * d.R;
+  const uint32_t stride = gridDim.z * blockDim.x;
+  constexpr int U = 4;   // loads in flight per thread
+  uint32_t j = blockIdx.z * blockDim.x + threadIdx.x;
+  for (; j + (U - 1) * stride < n; j += U * stride) {
+    uint64_t v[U];
+    uint32_t at[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+      const uint32_t jj = j + u * stride;
+      const uint32_t rb = jj / base, pos = jj - rb * base;
+      v[u] = src[(uint64_t)rb * d.W + s_list[pos]];
+      at[u] = pos * d.R + rb;
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) dst[at[u]] = v[u];
+  }
+  for (; j < n; j += stride) {
+    const uint32_t rb = j / base, pos = j - rb * base;
+    dst[pos * d.R + rb] = src[(uint64_t)rb * d.W + s_list[pos]];
   }
 }
 
@@ -281,6 +321,16 @@ __global__ void k_reset(cbaa_restore_stats* st, uint32_t* ones, uint32_t n_ones)
 // bits, a partial tuple whose AND already has more than Zmax zeros cannot
 // complete to an accepted tuple and is dropped: the accepted set is exactly
 // Alg. 3's. Lane q of the wave holds row blocks q, q+64, ...
+//
+// The wave's time is a chain of dependent memory round trips, so the walk is
+// arranged to keep that chain short:
+// * the first kListRegs * 64 entries of every hot list are held in registers,
+//   so the CP screens read no memory;
+// * complete CP-valid tuples are not checked one prefix at a time but queued,
+//   and a full queue is checked at once: the columns of all its tuples and the
+//   scan's zero counts of their VA columns are loaded together, then the VA
+//   columns of the tuples that pass;
+// * counts over the wave are summed with DPP row shifts, not LDS permutes.
 
 template <int RPL>
 struct Col {
@@ -295,6 +345,12 @@ __device__ inline void load_col(const Dims& d, const uint64_t* __restrict__ cube
     const uint32_t rb = lane_id() + q * kWave;
     c.w[q] = rb < d.R ? cube[((uint64_t)cs * d.R + rb) * d.W + slot] : ~0ull;
   }
+}
+
+template <int RPL>
+__device__ inline void and_col(Col<RPL>& a, const Col<RPL>& b) {
+#pragma unroll
+  for (int r = 0; r < RPL; ++r) a.w[r] &= b.w[r];
 }
 
 template <int RPL>
@@ -319,36 +375,65 @@ struct JoinArgs {
   const int32_t* zmax;
   const double* eps;
   cbaa_host* stage;
+  cbaa_host* wbuf;
+  uint32_t* wcnt;
   uint64_t capacity;
   cbaa_restore_stats* stats;
 };
 
-template <int NRA, int NVA>
-__device__ inline void emit_host(const Dims& d, const JoinArgs& ja, uint32_t cs, uint32_t lp,
-                                 uint32_t z) {
-  if (lane_id() == 0) {
-    const uint64_t idx =
-        __hip_atomic_fetch_add(&ja.stats->n_hosts, 1ull, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-    if (idx < ja.capacity) {
-      const double g = (double)d.g;
-      const double e = ja.eps[cs];
-      uint32_t zc = z;
-      uint8_t flags = 0;
-      if (zc == 0) {
-        zc = 1;
-        flags |= CBAA_FLAG_SATURATED;
-      }
-      double est = -g * log((double)zc / (g - g * e));
-      if (est < 0.0) est = 0.0;
-      cbaa_host h;
-      h.ip = fmix32_inverse((lp << d.r) | cs) ^ d.seed_mangle;
-      h.zeros = (uint16_t)z;
-      h.cs = (uint8_t)cs;
-      h.flags = flags;
-      h.est = est;
-      ja.stage[idx] = h;
-    }
+// Output entry of a restored host: IP reassembled from its sketch and LP
+// (Alg. 3), Z of its union column, the Thm. 2 estimate.
+__device__ inline cbaa_host make_host(const Dims& d, const JoinArgs& ja, uint32_t cs, uint32_t lp,
+                                      uint32_t z) {
+  const double g = (double)d.g;
+  const double e = ja.eps[cs];
+  uint32_t zc = z;
+  uint8_t flags = 0;
+  if (zc == 0) {
+    zc = 1;
+    flags |= CBAA_FLAG_SATURATED;
   }
+  double est = -g * log((double)zc / (g - g * e));
+  if (est < 0.0) est = 0.0;
+  cbaa_host h;
+  h.ip = fmix32_inverse((lp << d.r) | cs) ^ d.seed_mangle;
+  h.zeros = (uint16_t)z;
+  h.cs = (uint8_t)cs;
+  h.flags = flags;
+  h.est = est;
+  return h;
+}
+
+// Hosts a wave has found and not yet written: entry k sits in lane k. One
+// output counter shared by every wave serialises its increments (tens of ns
+// each), so a wave takes slots from it only when all 64 lanes are full; what
+// it holds at the end goes to its own region of wbuf, and k_compact appends
+// the regions after the counter's slots.
+struct Found {
+  uint32_t lp, z, cs;  // this lane's entry
+  uint32_t n;          // wave-uniform
+};
+
+__device__ inline void write_found(const Dims& d, const JoinArgs& ja, Found& f) {
+  uint64_t base = 0;
+  if (lane_id() == 0)
+    base = __hip_atomic_fetch_add(&ja.stats->n_hosts, (uint64_t)f.n, __ATOMIC_RELAXED,
+                                  __HIP_MEMORY_SCOPE_AGENT);
+  base = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(base >> 32)) << 32) |
+         (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)base);
+  const uint64_t idx = base + lane_id();
+  if (lane_id() < f.n && idx < ja.capacity) ja.stage[idx] = make_host(d, ja, f.cs, f.lp, f.z);
+  f.n = 0;
+}
+
+__device__ inline void emit_host(const Dims& d, const JoinArgs& ja, Found& f, uint32_t cs,
+                                 uint32_t lp, uint32_t z) {
+  if (lane_id() == f.n) {
+    f.lp = lp;
+    f.z = z;
+    f.cs = cs;
+  }
+  if (++f.n == (uint32_t)kWave) write_found(d, ja, f);
 }
 
 // Column `col` at position `pos` of the hot list of RA `level` in sketch cs:
@@ -368,24 +453,161 @@ __device__ inline void load_hot(const Dims& d, const JoinArgs& ja, uint32_t cs, 
   }
 }
 
-// Candidates that pass the CP screen are taken kBatch at a time so their
-// column loads are in flight together.
+// Candidates of an intermediate RA that pass the CP screen are taken kBatch
+// at a time so their column loads are in flight together; complete tuples
+// are queued kQueue<RPL> at a time (fewer when a column takes more
+// registers per lane).
 constexpr int kBatch = 4;
+constexpr int kListRegs = 4;
+template <int RPL>
+struct QueueLen {
+  static constexpr int value = RPL <= 2 ? 4 : (RPL == 4 ? 2 : 1);
+};
 
-template <int NRA, int NVA, int RPL, int LEVEL, bool G>
-__device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t zm,
-                       uint32_t (&t)[NRA], const Col<RPL>& acc, uint32_t& n_partial,
-                       uint32_t& n_tuples) {
-  const uint32_t cnt = ja.hcnt[cs * NRA + LEVEL];
-  const uint16_t* list = ja.hot + ((uint64_t)cs * NRA + LEVEL) * d.maxc_ra;
-  const uint32_t want_lo = t[LEVEL - 1] >> d.ep[LEVEL - 1];   // CP of hc_{l-1}
-  const uint32_t cp_mask = low_mask(d.cp[LEVEL - 1]);
-  const uint32_t want_hi = t[0] & low_mask(d.cp[NRA - 1]);    // first bits of hc_0
+// Everything one wave keeps while it walks the tuples of one hc0.
+template <int NRA, int RPL>
+struct Walk {
+  static constexpr int Q = QueueLen<RPL>::value;
+  uint32_t cs;
+  int32_t zm;
+  Col<RPL> c0;                       // column hc0, whole
+  uint32_t cnt[NRA];                 // |HC(i)|
+  const uint16_t* list[NRA];         // HC(i) in ascending order
+  uint32_t reg[NRA][kListRegs];      // HC(i)[lane + 64 k], k < kListRegs
+  uint32_t t[NRA];                   // columns of the tuple being extended
+  uint32_t tp[NRA];                  // their positions in HC(i)
+  uint32_t qc[Q][NRA];               // queued complete tuples in slots
+  uint32_t qp[Q][NRA];               // [0, nq): columns and positions (RA 0 unused)
+  int nq;
+  uint32_t n_partial, n_tuples;
+  Found found;
+};
+
+// Screens HC(LEVEL) 64 entries at a time: `round(cand, valid, base)` is
+// called with entry base + lane of the list. The first kListRegs rounds take
+// their entries from registers (shifted down one round at a time, so no
+// register is ever picked by a run-time index), later rounds from memory.
+template <int NRA, int RPL, int LEVEL, typename F>
+__device__ __attribute__((always_inline)) void for_list(const Walk<NRA, RPL>& w, F&& round) {
+  uint32_t r[kListRegs];
+#pragma unroll
+  for (int k = 0; k < kListRegs; ++k) r[k] = w.reg[LEVEL][k];
+  const uint32_t cnt = w.cnt[LEVEL];
   for (uint32_t base = 0; base < cnt; base += kWave) {
     const uint32_t j = base + lane_id();
-    const uint32_t cand = j < cnt ? list[j] : 0u;
-    bool ok = j < cnt && (cand & cp_mask) == want_lo;
-    if (LEVEL == NRA - 1) ok = ok && (cand >> d.ep[LEVEL]) == want_hi;
+    uint32_t cand;
+    if (base < (uint32_t)(kListRegs * kWave)) {
+      cand = r[0];
+#pragma unroll
+      for (int k = 0; k + 1 < kListRegs; ++k) r[k] = r[k + 1];
+    } else {
+      cand = j < cnt ? w.list[LEVEL][j] : 0u;
+    }
+    round(cand, j < cnt, base);
+  }
+}
+
+// Checks every queued tuple: AND of its RA columns with hc0, the VA
+// zero-count test, the VA columns, the count against Zmax, the output.
+template <int NRA, int NVA, int RPL, bool G>
+__device__ __attribute__((always_inline)) void check_queue(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w) {
+  constexpr int Q = Walk<NRA, RPL>::Q;
+  Col<RPL> acc[Q];
+  uint32_t lp[Q];
+  int32_t zva[Q];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (q >= w.nq) break;
+    // LP = concatenation of the EPs
+    uint32_t x = rotl_in(w.t[0] & low_mask(d.ep[0]), d.off[0], d.L);
+#pragma unroll
+    for (int i = 1; i < NRA; ++i) x |= rotl_in(w.qc[q][i] & low_mask(d.ep[i]), d.off[i], d.L);
+    lp[q] = x;
+    int32_t z = 0;
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) {
+      const int32_t zv = ja.zeros[(uint64_t)w.cs * d.W + d.aoff[NRA + v] + va_col(d, v, x)];
+      z = zv > z ? zv : z;
+    }
+    zva[q] = z;
+    acc[q] = w.c0;
+#pragma unroll
+    for (int i = 1; i < NRA; ++i) {
+      Col<RPL> c;
+      load_hot<RPL, G>(d, ja, w.cs, i, w.qp[q][i], w.qc[q][i], c);
+      and_col(acc[q], c);
+    }
+  }
+  // the union column is contained in every VA column, so it has at least as
+  // many zeros: a VA column over Zmax rejects the tuple before it is read
+  Col<RPL> vc[Q][NVA > 0 ? NVA : 1];
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (q >= w.nq) break;
+    if (zva[q] > w.zm) continue;
+#pragma unroll
+    for (int v = 0; v < NVA; ++v)
+      load_col<RPL>(d, ja.cube, w.cs, d.aoff[NRA + v] + va_col(d, v, lp[q]), vc[q][v]);
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    if (q >= w.nq) break;
+    if (zva[q] > w.zm) continue;
+#pragma unroll
+    for (int v = 0; v < NVA; ++v) and_col(acc[q], vc[q][v]);
+    ++w.n_tuples;
+    const uint32_t z = col_zeros<RPL>(d, acc[q]);
+    if ((int32_t)z <= w.zm) emit_host(d, ja, w.found, w.cs, lp[q], z);
+  }
+  w.nq = 0;
+}
+
+// Last RA: every CP-valid candidate completes a tuple, which is queued.
+template <int NRA, int NVA, int RPL, bool G>
+__device__ __attribute__((always_inline)) void extend_last(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w) {
+  constexpr int L = NRA - 1;
+  constexpr int Q = Walk<NRA, RPL>::Q;
+  const uint32_t want_lo = w.t[L - 1] >> d.ep[L - 1];      // CP of hc_{l-1}
+  const uint32_t cp_mask = low_mask(d.cp[L - 1]);
+  const uint32_t want_hi = w.t[0] & low_mask(d.cp[L]);     // first bits of hc_0
+  for_list<NRA, RPL, L>(w, [&](uint32_t cand, bool valid, uint32_t base) {
+    const bool ok = valid && (cand & cp_mask) == want_lo && (cand >> d.ep[L]) == want_hi;
+    uint64_t m = __ballot(ok);
+    while (m) {
+      const int l = __builtin_ctzll(m);
+      m &= m - 1;
+      const uint32_t h = (uint32_t)__builtin_amdgcn_readlane((int)cand, l);
+      // the queue shifts up one slot and the new tuple enters slot 0: no slot
+      // is chosen by a run-time index
+#pragma unroll
+      for (int q = Q - 1; q > 0; --q) {
+#pragma unroll
+        for (int i = 1; i < NRA; ++i) {
+          w.qc[q][i] = w.qc[q - 1][i];
+          w.qp[q][i] = w.qp[q - 1][i];
+        }
+      }
+#pragma unroll
+      for (int i = 1; i < L; ++i) {
+        w.qc[0][i] = w.t[i];
+        w.qp[0][i] = w.tp[i];
+      }
+      w.qc[0][L] = h;
+      w.qp[0][L] = base + (uint32_t)l;
+      if (++w.nq == Q) check_queue<NRA, NVA, RPL, G>(d, ja, w);
+    }
+  });
+}
+
+// Intermediate RA LEVEL (0 < LEVEL < NRA - 1): CP screen against hc_{l-1},
+// then the AND with the prefix `acc`, pruned above Zmax.
+template <int NRA, int NVA, int RPL, int LEVEL, bool G>
+__device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w,
+                       const Col<RPL>& acc) {
+  const uint32_t want_lo = w.t[LEVEL - 1] >> d.ep[LEVEL - 1];
+  const uint32_t cp_mask = low_mask(d.cp[LEVEL - 1]);
+  for_list<NRA, RPL, LEVEL>(w, [&](uint32_t cand, bool valid, uint32_t base) {
+    const bool ok = valid && (cand & cp_mask) == want_lo;
     uint64_t m = __ballot(ok);
     while (m) {
       uint32_t h[kBatch], pos[kBatch];
@@ -405,46 +627,38 @@ __device__ void extend(const Dims& d, const JoinArgs& ja, uint32_t cs, int32_t z
       Col<RPL> c[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q)
-        if (q < nb) load_hot<RPL, G>(d, ja, cs, LEVEL, pos[q], h[q], c[q]);
+        if (q < nb) load_hot<RPL, G>(d, ja, w.cs, LEVEL, pos[q], h[q], c[q]);
+      uint32_t keep = 0;   // candidates whose partial AND is within Zmax
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
         if (q >= nb) break;
+        and_col(c[q], acc);
+        ++w.n_partial;
+        if ((int32_t)col_zeros<RPL>(d, c[q]) <= w.zm) keep |= 1u << q;
+      }
+      // the kept candidates are extended in order; each step shifts the
+      // batch down one slot, so the one at hand is always slot 0 and the
+      // deeper levels are emitted once, not once per slot
+#pragma unroll 1
+      for (int q = 0; q < nb; ++q) {
+        if (keep & 1u) {
+          w.t[LEVEL] = h[0];
+          w.tp[LEVEL] = pos[0];
+          if constexpr (LEVEL + 1 < NRA - 1)
+            extend<NRA, NVA, RPL, LEVEL + 1, G>(d, ja, w, c[0]);
+          else
+            extend_last<NRA, NVA, RPL, G>(d, ja, w);
+        }
+        keep >>= 1;
 #pragma unroll
-        for (int r = 0; r < RPL; ++r) c[q].w[r] &= acc.w[r];
-        t[LEVEL] = h[q];
-        if constexpr (LEVEL < NRA - 1) {
-          ++n_partial;
-          if ((int32_t)col_zeros<RPL>(d, c[q]) > zm) continue;
-          extend<NRA, NVA, RPL, LEVEL + 1, G>(d, ja, cs, zm, t, c[q], n_partial, n_tuples);
-        } else {
-          // complete CP-valid tuple: LP = concatenation of the EPs
-          uint32_t lp = 0;
-#pragma unroll
-          for (int i = 0; i < NRA; ++i) lp |= rotl_in(t[i] & low_mask(d.ep[i]), d.off[i], d.L);
-          // the union column is contained in every VA column, so it has at
-          // least as many zeros: a VA column over Zmax rejects the tuple
-          // before any of its words are read
-          int32_t zva = 0;
-#pragma unroll
-          for (int v = 0; v < NVA; ++v) {
-            const int32_t zv = ja.zeros[(uint64_t)cs * d.W + d.aoff[NRA + v] + va_col(d, v, lp)];
-            zva = zv > zva ? zv : zva;
-          }
-          if (zva > zm) continue;
-#pragma unroll
-          for (int v = 0; v < NVA; ++v) {
-            Col<RPL> vc;
-            load_col<RPL>(d, ja.cube, cs, d.aoff[NRA + v] + va_col(d, v, lp), vc);
-#pragma unroll
-            for (int r = 0; r < RPL; ++r) c[q].w[r] &= vc.w[r];
-          }
-          ++n_tuples;
-          const uint32_t z = col_zeros<RPL>(d, c[q]);
-          if ((int32_t)z <= zm) emit_host<NRA, NVA>(d, ja, cs, lp, z);
+        for (int k = 0; k + 1 < kBatch; ++k) {
+          c[k] = c[k + 1];
+          h[k] = h[k + 1];
+          pos[k] = pos[k + 1];
         }
       }
     }
-  }
+  });
 }
 
 // G: the variant that reads gathered columns. Both variants are launched;
@@ -471,29 +685,101 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
   const uint32_t waves_per_block = kJoinBlock / kWave;
   const uint32_t gw = blockIdx.x * waves_per_block + threadIdx.x / kWave;
   const uint32_t nwaves = gridDim.x * waves_per_block;
-  uint32_t n_partial = 0, n_tuples = 0;
+  Walk<NRA, RPL> w;
+  w.n_partial = 0;
+  w.n_tuples = 0;
+  w.found.n = 0;
   for (uint32_t item = gw; item < total; item += nwaves) {
     uint32_t lo = 0, hi = d.S;  // largest cs with pre[cs] <= item
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) / 2;
       if (pre[mid] <= item) lo = mid; else hi = mid;
     }
-    const uint32_t cs = lo;
-    const uint32_t pos0 = item - pre[cs];
-    const uint32_t hc0 = ja.hot[((uint64_t)cs * NRA + 0) * d.maxc_ra + pos0];
-    const int32_t zm = ja.zmax[cs];
-    uint32_t t[NRA];
-    t[0] = hc0;
-    Col<RPL> c0;
-    load_hot<RPL, G>(d, ja, cs, 0, pos0, hc0, c0);
-    extend<NRA, NVA, RPL, 1, G>(d, ja, cs, zm, t, c0, n_partial, n_tuples);
+    w.cs = lo;
+    const uint32_t pos0 = item - pre[w.cs];
+    w.zm = ja.zmax[w.cs];
+#pragma unroll
+    for (int i = 0; i < NRA; ++i) {
+      w.cnt[i] = ja.hcnt[w.cs * NRA + i];
+      w.list[i] = ja.hot + ((uint64_t)w.cs * NRA + i) * d.maxc_ra;
+    }
+    w.t[0] = w.list[0][pos0];
+    w.tp[0] = pos0;
+#pragma unroll
+    for (int i = 1; i < NRA; ++i) {
+#pragma unroll
+      for (int k = 0; k < kListRegs; ++k) {
+        const uint32_t j = (uint32_t)k * kWave + lane_id();
+        w.reg[i][k] = j < w.cnt[i] ? w.list[i][j] : 0u;
+      }
+    }
+    load_hot<RPL, G>(d, ja, w.cs, 0, pos0, w.t[0], w.c0);
+    w.nq = 0;
+    if constexpr (NRA > 2)
+      extend<NRA, NVA, RPL, 1, G>(d, ja, w, w.c0);
+    else
+      extend_last<NRA, NVA, RPL, G>(d, ja, w);
+    if (w.nq) check_queue<NRA, NVA, RPL, G>(d, ja, w);
   }
-  if (lane_id() == 0 && (n_partial | n_tuples)) {
-    __hip_atomic_fetch_add(&ja.stats->partial_checked, (uint64_t)n_partial, __ATOMIC_RELAXED,
+  if (lane_id() < w.found.n)
+    ja.wbuf[(uint64_t)gw * kWave + lane_id()] = make_host(d, ja, w.found.cs, w.found.lp, w.found.z);
+  if (lane_id() == 0) ja.wcnt[gw] = w.found.n;
+  if (lane_id() == 0 && (w.n_partial | w.n_tuples)) {
+    __hip_atomic_fetch_add(&ja.stats->partial_checked, (uint64_t)w.n_partial, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
-    __hip_atomic_fetch_add(&ja.stats->tuples_checked, (uint64_t)n_tuples, __ATOMIC_RELAXED,
+    __hip_atomic_fetch_add(&ja.stats->tuples_checked, (uint64_t)w.n_tuples, __ATOMIC_RELAXED,
                            __HIP_MEMORY_SCOPE_AGENT);
   }
+}
+
+// Appends every join wave's region of wbuf, in wave order, after the slots
+// the waves took from the output counter, and sets the counter to the total.
+// One block: the per-wave counts are prefixed in LDS, then each thread copies
+// entries e, e + kCompactBlock, ..., finding the region of e by binary search.
+constexpr int kCompactBlock = 1024;
+__global__ __launch_bounds__(kCompactBlock) void k_compact(const cbaa_host* __restrict__ wbuf,
+                                                           const uint32_t* __restrict__ wcnt,
+                                                           cbaa_restore_stats* stats,
+                                                           cbaa_host* stage, uint64_t capacity) {
+  constexpr uint32_t kPer = kJoinWaves / kCompactBlock;
+  static_assert(kPer * kCompactBlock == kJoinWaves, "regions split evenly over threads");
+  __shared__ uint32_t part[kCompactBlock];
+  __shared__ uint32_t pre[kJoinWaves];   // first entry of each region
+  const uint32_t t = threadIdx.x;
+  uint32_t c[kPer], sum = 0;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    c[k] = wcnt[t * kPer + k];
+    sum += c[k];
+  }
+  part[t] = sum;
+  __syncthreads();
+  for (uint32_t o = 1; o < kCompactBlock; o <<= 1) {   // inclusive scan
+    const uint32_t v = t >= o ? part[t - o] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - sum;
+#pragma unroll
+  for (uint32_t k = 0; k < kPer; ++k) {
+    pre[t * kPer + k] = run;
+    run += c[k];
+  }
+  const uint32_t total = part[kCompactBlock - 1];
+  const uint64_t flushed = stats->n_hosts;   // slots the waves took while joining
+  __syncthreads();
+  for (uint32_t e = t; e < total; e += kCompactBlock) {
+    uint32_t lo = 0, hi = kJoinWaves;   // last region starting at or before e
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (pre[mid] <= e) lo = mid; else hi = mid;
+    }
+    const uint64_t idx = flushed + e;
+    if (idx < capacity) stage[idx] = wbuf[(uint64_t)lo * kWave + (e - pre[lo])];
+  }
+  __syncthreads();
+  if (t == 0) stats->n_hosts = flushed + total;
 }
 
 // ---- ordering of the restored list --------------------------------------
@@ -782,7 +1068,7 @@ int run_scan(const Dims& d, const uint64_t* cube, uint16_t* zeros, uint32_t* one
 
 template <int NRA, int NVA>
 int dispatch_rpl_join(const Dims& d, const JoinArgs& ja, hipStream_t s) {
-  const uint32_t grid = 2048;  // 8 waves per CU on 256 CUs; waves stride over the work list
+  const uint32_t grid = kJoinWaves;  // waves; they stride over the work list
 #define CBAA_JOIN(RPL)                                                                  \
   if (d.R <= RPL * kWave) {                                                             \
     hipLaunchKernelGGL((k_join<NRA, NVA, RPL, true>), dim3(grid / (kJoinBlock / kWave)), \
@@ -877,13 +1163,16 @@ int restore_after_scan(const Dims& d, const uint64_t* cube, double x, int rule,
                        const RestoreScratch& rs, uint64_t capacity, cbaa_host* out,
                        cbaa_restore_stats* stats, hipStream_t s) {
   int rc;
-  hipLaunchKernelGGL(k_prepare, dim3(d.S, d.n_ra), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
-                     rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats, cube, rs.hcol, rs.gcap,
-                     rs.gfit);
+  hipLaunchKernelGGL(k_prepare, dim3(d.S, d.n_ra, kPrepParts), dim3(kPrepBlock), 0, s, d,
+                     rs.zeros, rs.ones, rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats, cube,
+                     rs.hcol, rs.gcap, rs.gfit);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
   JoinArgs ja{cube, rs.zeros, rs.hot, rs.hcol, rs.gfit, rs.gcap, rs.hcnt, rs.zmax, rs.eps,
-              rs.stage, capacity, stats};
+              rs.stage, rs.wbuf, rs.wcnt, capacity, stats};
   if ((rc = run_join(d, ja, s)) != CBAA_OK) return rc;
+  hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactBlock), 0, s, rs.wbuf, rs.wcnt, stats,
+                     rs.stage, capacity);
+  if ((rc = check_launch("compact launch")) != CBAA_OK) return rc;
   if (capacity == 0) return CBAA_OK;
   const uint64_t small = capacity < kSmallSort ? capacity : kSmallSort;
   hipLaunchKernelGGL(k_rank_small, dim3((uint32_t)((small + 3) / 4)), dim3(256), 0, s, rs.stage,
