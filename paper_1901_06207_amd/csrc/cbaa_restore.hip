@@ -92,6 +92,21 @@ __device__ inline uint32_t wave_sum(uint32_t v) {
 
 __device__ inline uint32_t lane_id() { return __lane_id(); }
 
+// Inclusive prefix sum over the wave: DPP row shifts give the prefix inside
+// each row of 16 lanes (as in wave_sum), then the totals of the rows before a
+// lane's row are added from wave-uniform reads.
+__device__ inline uint32_t wave_inclusive_scan(uint32_t v) {
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x111, 0xf, 0xf, false);  // row_shr:1
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x112, 0xf, 0xf, false);  // row_shr:2
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x114, 0xf, 0xf, false);  // row_shr:4
+  v += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, 0x118, 0xf, 0xf, false);  // row_shr:8
+  const uint32_t r0 = (uint32_t)__builtin_amdgcn_readlane((int)v, 15);
+  const uint32_t r1 = (uint32_t)__builtin_amdgcn_readlane((int)v, 31);
+  const uint32_t r2 = (uint32_t)__builtin_amdgcn_readlane((int)v, 47);
+  const uint32_t row = lane_id() >> 4;
+  return v + (row > 0 ? r0 : 0u) + (row > 1 ? r1 : 0u) + (row > 2 ? r2 : 0u);
+}
+
 // ---- per-column zero counts ---------------------------------------------
 // Thread (cs, w..w+1): popcounts of two neighbouring columns' words over all
 // R row blocks (16 loads in flight); a wave reads 1 KiB contiguous per row
@@ -734,41 +749,45 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
 
 // Appends every join wave's region of wbuf, in wave order, after the slots
 // the waves took from the output counter, and sets the counter to the total.
-// One block: the per-wave counts are prefixed in LDS, then each thread copies
-// entries e, e + kCompactBlock, ..., finding the region of e by binary search.
+// One block: the per-wave counts are prefixed (wave scans, then the wave
+// totals), then each thread copies entries e, e + kCompactBlock, ..., finding
+// the region of e by binary search.
 constexpr int kCompactBlock = 1024;
 __global__ __launch_bounds__(kCompactBlock) void k_compact(const cbaa_host* __restrict__ wbuf,
                                                            const uint32_t* __restrict__ wcnt,
                                                            cbaa_restore_stats* stats,
                                                            cbaa_host* stage, uint64_t capacity) {
   constexpr uint32_t kPer = kJoinWaves / kCompactBlock;
+  constexpr uint32_t kWaves = kCompactBlock / kWave;
   static_assert(kPer * kCompactBlock == kJoinWaves, "regions split evenly over threads");
-  __shared__ uint32_t part[kCompactBlock];
+  __shared__ uint32_t wave_tot[kWaves];
   __shared__ uint32_t pre[kJoinWaves];   // first entry of each region
-  const uint32_t t = threadIdx.x;
+  __shared__ uint64_t s_flushed;         // slots the waves took while joining
+  const uint32_t t = threadIdx.x, wid = t / kWave;
   uint32_t c[kPer], sum = 0;
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     c[k] = wcnt[t * kPer + k];
     sum += c[k];
   }
-  part[t] = sum;
+  if (t == 0) s_flushed = stats->n_hosts;
+  const uint32_t incl = wave_inclusive_scan(sum);
+  if (lane_id() == kWave - 1) wave_tot[wid] = incl;
   __syncthreads();
-  for (uint32_t o = 1; o < kCompactBlock; o <<= 1) {   // inclusive scan
-    const uint32_t v = t >= o ? part[t - o] : 0u;
-    __syncthreads();
-    part[t] += v;
-    __syncthreads();
+  uint32_t run = incl - sum, total = 0;
+  for (uint32_t w = 0; w < kWaves; ++w) {
+    const uint32_t x = wave_tot[w];
+    if (w < wid) run += x;
+    total += x;
   }
-  uint32_t run = part[t] - sum;
 #pragma unroll
   for (uint32_t k = 0; k < kPer; ++k) {
     pre[t * kPer + k] = run;
     run += c[k];
   }
-  const uint32_t total = part[kCompactBlock - 1];
-  const uint64_t flushed = stats->n_hosts;   // slots the waves took while joining
-  __syncthreads();
+  __syncthreads();   // pre and s_flushed complete
+  const uint64_t flushed = s_flushed;
+  if (t == 0) stats->n_hosts = flushed + total;
   for (uint32_t e = t; e < total; e += kCompactBlock) {
     uint32_t lo = 0, hi = kJoinWaves;   // last region starting at or before e
     while (hi - lo > 1) {
@@ -778,8 +797,6 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(const cbaa_host* __re
     const uint64_t idx = flushed + e;
     if (idx < capacity) stage[idx] = wbuf[(uint64_t)lo * kWave + (e - pre[lo])];
   }
-  __syncthreads();
-  if (t == 0) stats->n_hosts = flushed + total;
 }
 
 // ---- ordering of the restored list --------------------------------------
