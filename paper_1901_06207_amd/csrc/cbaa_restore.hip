@@ -452,11 +452,12 @@ __device__ inline void emit_host(const Dims& d, const JoinArgs& ja, Found& f, ui
 }
 
 // Column `col` at position `pos` of the hot list of RA `level` in sketch cs:
-// from the gathered copy (G) or straight from the cube.
-template <int RPL, bool G>
-__device__ inline void load_hot(const Dims& d, const JoinArgs& ja, uint32_t cs, uint32_t level,
-                                uint32_t pos, uint32_t col, Col<RPL>& c) {
-  if constexpr (G) {
+// from the gathered copy when every list of the restore fit the gather
+// buffer (`gathered`, uniform over the grid), else straight from the cube.
+template <int RPL>
+__device__ inline void load_hot(const Dims& d, const JoinArgs& ja, bool gathered, uint32_t cs,
+                                uint32_t level, uint32_t pos, uint32_t col, Col<RPL>& c) {
+  if (gathered) {
     const uint64_t* src = ja.hcol + (((uint64_t)cs * d.n_ra + level) * ja.gcap + pos) * d.R;
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
@@ -485,6 +486,7 @@ struct Walk {
   static constexpr int Q = QueueLen<RPL>::value;
   uint32_t cs;
   int32_t zm;
+  bool gathered;                     // hot columns read from the gathered copy
   Col<RPL> c0;                       // column hc0, whole
   uint32_t cnt[NRA];                 // |HC(i)|
   const uint16_t* list[NRA];         // HC(i) in ascending order
@@ -524,7 +526,7 @@ __device__ __attribute__((always_inline)) void for_list(const Walk<NRA, RPL>& w,
 
 // Checks every queued tuple: AND of its RA columns with hc0, the VA
 // zero-count test, the VA columns, the count against Zmax, the output.
-template <int NRA, int NVA, int RPL, bool G>
+template <int NRA, int NVA, int RPL>
 __device__ __attribute__((always_inline)) void check_queue(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w) {
   constexpr int Q = Walk<NRA, RPL>::Q;
   Col<RPL> acc[Q];
@@ -549,7 +551,7 @@ __device__ __attribute__((always_inline)) void check_queue(const Dims& d, const 
 #pragma unroll
     for (int i = 1; i < NRA; ++i) {
       Col<RPL> c;
-      load_hot<RPL, G>(d, ja, w.cs, i, w.qp[q][i], w.qc[q][i], c);
+      load_hot<RPL>(d, ja, w.gathered, w.cs, i, w.qp[q][i], w.qc[q][i], c);
       and_col(acc[q], c);
     }
   }
@@ -578,7 +580,7 @@ __device__ __attribute__((always_inline)) void check_queue(const Dims& d, const 
 }
 
 // Last RA: every CP-valid candidate completes a tuple, which is queued.
-template <int NRA, int NVA, int RPL, bool G>
+template <int NRA, int NVA, int RPL>
 __device__ __attribute__((always_inline)) void extend_last(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w) {
   constexpr int L = NRA - 1;
   constexpr int Q = Walk<NRA, RPL>::Q;
@@ -609,14 +611,14 @@ __device__ __attribute__((always_inline)) void extend_last(const Dims& d, const 
       }
       w.qc[0][L] = h;
       w.qp[0][L] = base + (uint32_t)l;
-      if (++w.nq == Q) check_queue<NRA, NVA, RPL, G>(d, ja, w);
+      if (++w.nq == Q) check_queue<NRA, NVA, RPL>(d, ja, w);
     }
   });
 }
 
 // Intermediate RA LEVEL (0 < LEVEL < NRA - 1): CP screen against hc_{l-1},
 // then the AND with the prefix `acc`, pruned above Zmax.
-template <int NRA, int NVA, int RPL, int LEVEL, bool G>
+template <int NRA, int NVA, int RPL, int LEVEL>
 __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w,
                        const Col<RPL>& acc) {
   const uint32_t want_lo = w.t[LEVEL - 1] >> d.ep[LEVEL - 1];
@@ -642,7 +644,7 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
       Col<RPL> c[kBatch];
 #pragma unroll
       for (int q = 0; q < kBatch; ++q)
-        if (q < nb) load_hot<RPL, G>(d, ja, w.cs, LEVEL, pos[q], h[q], c[q]);
+        if (q < nb) load_hot<RPL>(d, ja, w.gathered, w.cs, LEVEL, pos[q], h[q], c[q]);
       uint32_t keep = 0;   // candidates whose partial AND is within Zmax
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
@@ -660,9 +662,9 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
           w.t[LEVEL] = h[0];
           w.tp[LEVEL] = pos[0];
           if constexpr (LEVEL + 1 < NRA - 1)
-            extend<NRA, NVA, RPL, LEVEL + 1, G>(d, ja, w, c[0]);
+            extend<NRA, NVA, RPL, LEVEL + 1>(d, ja, w, c[0]);
           else
-            extend_last<NRA, NVA, RPL, G>(d, ja, w);
+            extend_last<NRA, NVA, RPL>(d, ja, w);
         }
         keep >>= 1;
 #pragma unroll
@@ -676,16 +678,13 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
   });
 }
 
-// G: the variant that reads gathered columns. Both variants are launched;
-// each first checks whether every hot list fit the gather buffer and only
-// the matching one proceeds (the test is uniform over the grid).
-template <int NRA, int NVA, int RPL, bool G>
+template <int NRA, int NVA, int RPL>
 __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
   __shared__ uint32_t pre[257];
+  // hot columns come from the gathered copy only if every list fit it
   uint32_t missed = 0;
   for (uint32_t i = lane_id(); i < d.S * NRA; i += kWave) missed |= ja.gfit[i] ^ 1u;
   const bool all_fit = __ballot(missed != 0) == 0;
-  if (all_fit != G) return;
   // prefix over sketches of |HC(0)|: flattened work list of (cs, hc0)
   if (threadIdx.x == 0) {
     uint32_t acc = 0;
@@ -701,6 +700,7 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
   const uint32_t gw = blockIdx.x * waves_per_block + threadIdx.x / kWave;
   const uint32_t nwaves = gridDim.x * waves_per_block;
   Walk<NRA, RPL> w;
+  w.gathered = all_fit;
   w.n_partial = 0;
   w.n_tuples = 0;
   w.found.n = 0;
@@ -728,13 +728,13 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
         w.reg[i][k] = j < w.cnt[i] ? w.list[i][j] : 0u;
       }
     }
-    load_hot<RPL, G>(d, ja, w.cs, 0, pos0, w.t[0], w.c0);
+    load_hot<RPL>(d, ja, w.gathered, w.cs, 0, pos0, w.t[0], w.c0);
     w.nq = 0;
     if constexpr (NRA > 2)
-      extend<NRA, NVA, RPL, 1, G>(d, ja, w, w.c0);
+      extend<NRA, NVA, RPL, 1>(d, ja, w, w.c0);
     else
-      extend_last<NRA, NVA, RPL, G>(d, ja, w);
-    if (w.nq) check_queue<NRA, NVA, RPL, G>(d, ja, w);
+      extend_last<NRA, NVA, RPL>(d, ja, w);
+    if (w.nq) check_queue<NRA, NVA, RPL>(d, ja, w);
   }
   if (lane_id() < w.found.n)
     ja.wbuf[(uint64_t)gw * kWave + lane_id()] = make_host(d, ja, w.found.cs, w.found.lp, w.found.z);
@@ -1088,9 +1088,7 @@ int dispatch_rpl_join(const Dims& d, const JoinArgs& ja, hipStream_t s) {
   const uint32_t grid = kJoinWaves;  // waves; they stride over the work list
 #define CBAA_JOIN(RPL)                                                                  \
   if (d.R <= RPL * kWave) {                                                             \
-    hipLaunchKernelGGL((k_join<NRA, NVA, RPL, true>), dim3(grid / (kJoinBlock / kWave)), \
-                       dim3(kJoinBlock), 0, s, d, ja);                                  \
-    hipLaunchKernelGGL((k_join<NRA, NVA, RPL, false>), dim3(grid / (kJoinBlock / kWave)),\
+    hipLaunchKernelGGL((k_join<NRA, NVA, RPL>), dim3(grid / (kJoinBlock / kWave)),      \
                        dim3(kJoinBlock), 0, s, d, ja);                                  \
     return check_launch("join launch");                                                \
   }
