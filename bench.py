@@ -81,6 +81,8 @@ def parse():
     ap.add_argument("--workload", choices=["core-edge", "batched"], default="core-edge",
                     help="batched: 32 router streams of 1M-64M packets in one graph replay")
     ap.add_argument("--streams", type=int, default=32)
+    ap.add_argument("--store-merged", action="store_true",
+                    help="the window end also stores each side's merged (global) cube")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -154,9 +156,13 @@ def main():
         cbaa.cbaa_update_batch(cfg, table, scratch_u, tuning, stream)
         if timed:
             mark("window_end", stream)
-        # global server: OR-merge the routers' cubes and restore, per side
+        # global server: OR-merge the routers' cubes and restore, per side.
+        # The merged cube is an intermediate of the restore: unless asked to,
+        # it is not stored, and the restore reads each column it needs as the
+        # OR of the router cubes.
         for i, cube in enumerate((g_src, g_dst)):
-            cbaa.cbaa_merge_restore(cfg, cube, [x[i] for x in local], args.theta, cbaa.THR_THM2,
+            cbaa.cbaa_merge_restore(cfg, cube if args.store_merged else None,
+                                    [x[i] for x in local], args.theta, cbaa.THR_THM2,
                                     scratch_r[i], outs[i], capacity, stats[i], stream)
         if timed:
             mark("copy", stream)
@@ -232,6 +238,17 @@ def main():
     torch.cuda.synchronize(dev)
     merge_ms = span("m0", "m1")
     restore_ms = span("m1", "m2") / 2.0
+    # the window end in the other mode (merged cube stored or not), per side
+    ev.clear()
+    for _ in range(phase_steps):
+        mark("w0", stream)
+        for i, cube in enumerate((g_src, g_dst)):
+            cbaa.cbaa_merge_restore(cfg, None if args.store_merged else cube,
+                                    [x[i] for x in local], args.theta, cbaa.THR_THM2,
+                                    scratch_r[i], outs[i], capacity, stats[i], stream)
+        mark("w1", stream)
+    torch.cuda.synchronize(dev)
+    window_end_other_ms = span("w0", "w1") / 2.0
     upd_gpkts = trace.n / (upd_ms.mean() * 1e-3) / 1e9
 
     # roofline of the dominant kernel set, the batched update call: algorithmic
@@ -310,11 +327,15 @@ def main():
             "packets": trace.n, "routers": args.routers, "seed": args.seed,
             "launch": "eager" if graph is None else "hip-graph",
             "tuning": tuning or "default",
+            "merged_cube": ("stored" if args.store_merged else
+                            "not stored: the restore reads columns as the OR of the router cubes"),
         },
         "phases": {
             "update_ms": round(float(upd_ms.mean()), 4),
             "update_gpkt_s": round(float(upd_gpkts), 3),
             "window_end_ms_per_side": round(float(window_end_ms.mean()), 4),
+            ("window_end_unstored_ms_per_side" if args.store_merged
+             else "window_end_stored_ms_per_side"): round(float(window_end_other_ms.mean()), 4),
             "merge_ms": round(float(merge_ms.mean()), 4),
             "restore_ms_per_window": round(float(restore_ms.mean()), 4),
             "restore_ms_p99": round(float(np.percentile(restore_ms, 99)), 4),

@@ -248,7 +248,11 @@ int cbaa_restore(const cbaa_config* h_cfg, const void* d_cube, double theta, int
  * per-column zero counts the restore starts from are computed in one pass
  * over the sources, so the merged cube is written once and never re-read
  * for the counts; larger k merges first. Arguments and results as for
- * cbaa_merge_or and cbaa_restore. */
+ * cbaa_merge_or and cbaa_restore.
+ * d_dst may be NULL when k <= 16: the merged cube is then not stored, and
+ * the restore reads each column it needs (hot columns, VA columns) as the OR
+ * of the sources. The restored list and stats are those of the stored case.
+ * NULL with k > 16 returns CBAA_EINVAL. */
 int cbaa_merge_restore(const cbaa_config* h_cfg, void* d_dst, const void* const* h_srcs, int k,
                        double theta, int thr_rule, void* d_scratch, uint64_t scratch_bytes,
                        cbaa_host* d_out, uint64_t capacity, cbaa_restore_stats* d_stats,

@@ -325,12 +325,15 @@ def cbaa_restore(cfg, cube: torch.Tensor, theta: float, rule: int, scratch: torc
                               _dev_ptr(stats, "stats"), _stream(stream)), "cbaa_restore")
 
 
-def cbaa_merge_restore(cfg, dst: torch.Tensor, srcs: Sequence[torch.Tensor], theta: float,
-                       rule: int, scratch: torch.Tensor, out: Optional[torch.Tensor],
+def cbaa_merge_restore(cfg, dst: Optional[torch.Tensor], srcs: Sequence[torch.Tensor],
+                       theta: float, rule: int, scratch: torch.Tensor, out: Optional[torch.Tensor],
                        capacity: int, stats: torch.Tensor, stream=None) -> None:
+    """dst None: the merged cube is not stored (at most 16 sources)."""
     arr = (C.c_void_p * len(srcs))(*[_dev_ptr(x, "src") for x in srcs])
     sb = scratch.numel() * scratch.element_size()
-    _check(lib().cbaa_merge_restore(C.byref(_cfg(cfg)), _dev_ptr(dst, "dst"), arr, len(srcs),
+    _check(lib().cbaa_merge_restore(C.byref(_cfg(cfg)),
+                                    _dev_ptr(dst, "dst") if dst is not None else None,
+                                    arr, len(srcs),
                                     float(theta), rule, _dev_ptr(scratch, "scratch"), sb,
                                     _dev_ptr(out, "out") if capacity else None, capacity,
                                     _dev_ptr(stats, "stats"), _stream(stream)),

@@ -260,8 +260,11 @@ int cbaa_update_batch(const cbaa_config* cfg, const cbaa_stream_batch* h, int k,
 int cbaa_merge_or(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
                   void* stream) {
   CHECK_DIMS(cfg, d);
-  REQUIRE(d_dst && ((uintptr_t)d_dst & 15u) == 0, "destination must be 16-byte aligned");
+  // a null destination (merge not stored) is served by the one-pass scan,
+  // which takes up to 16 sources
+  REQUIRE(((uintptr_t)d_dst & 15u) == 0, "destination must be 16-byte aligned");
   REQUIRE(h_srcs && k >= 1, "need at least one source cube");
+  REQUIRE(d_dst || k <= 16, "more than 16 source cubes need a destination cube");
   for (int i = 0; i < k; ++i)
     REQUIRE(h_srcs[i] && ((uintptr_t)h_srcs[i] & 15u) == 0, "source %d null or not 16-byte aligned", i);
   return launch_merge_or(d, (uint64_t*)d_dst, (const uint64_t* const*)h_srcs, k, (hipStream_t)stream);
@@ -306,8 +309,11 @@ int cbaa_merge_restore(const cbaa_config* cfg, void* d_dst, const void* const* h
                        cbaa_host* d_out, uint64_t capacity, cbaa_restore_stats* d_stats,
                        void* stream) {
   CHECK_DIMS(cfg, d);
-  REQUIRE(d_dst && ((uintptr_t)d_dst & 15u) == 0, "destination must be 16-byte aligned");
+  // a null destination (merge not stored) is served by the one-pass scan,
+  // which takes up to 16 sources
+  REQUIRE(((uintptr_t)d_dst & 15u) == 0, "destination must be 16-byte aligned");
   REQUIRE(h_srcs && k >= 1, "need at least one source cube");
+  REQUIRE(d_dst || k <= 16, "more than 16 source cubes need a destination cube");
   for (int i = 0; i < k; ++i)
     REQUIRE(h_srcs[i] && ((uintptr_t)h_srcs[i] & 15u) == 0, "source %d null or not 16-byte aligned", i);
   REQUIRE(thr_rule == CBAA_THR_THM2 || thr_rule == CBAA_THR_PAPER, "unknown threshold rule");

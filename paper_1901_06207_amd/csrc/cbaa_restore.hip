@@ -155,13 +155,27 @@ __global__ __launch_bounds__(kScanBlock) void k_column_zeros(Dims d, const uint4
 
 // The global server's OR-merge and the column scan in one pass: the same
 // walk as k_column_zeros, each 16-byte unit being the OR of up to 16 source
-// cubes, stored to dst and then counted. dst may be one of the sources: every
-// unit is read from all sources by the thread that writes it.
+// cubes, stored to dst (unless dst is null) and then counted. dst may be one
+// of the sources: every unit is read from all sources by the thread that
+// writes it.
 constexpr int kMergeScanSources = 16;
 
 struct MergeSrc {
   const uint4* p[kMergeScanSources];
 };
+
+// Where the restore reads cube words after the scan: the OR of k cubes
+// (k = 1: one stored cube; k > 1: router cubes whose merge was not stored).
+struct CubeSrc {
+  const uint64_t* p[kMergeScanSources];
+  int k;
+};
+
+__device__ inline uint64_t cube_word(const CubeSrc& c, uint64_t i) {
+  uint64_t v = c.p[0][i];
+  for (int j = 1; j < c.k; ++j) v |= c.p[j][i];
+  return v;
+}
 
 __global__ __launch_bounds__(kScanBlock) void k_merge_scan(Dims d, MergeSrc src, int k, uint4* dst,
                                                            uint32_t* __restrict__ zeros2,
@@ -194,7 +208,7 @@ __global__ __launch_bounds__(kScanBlock) void k_merge_scan(Dims d, MergeSrc src,
 #pragma unroll
       for (uint32_t u = 0; u < kU; ++u) {
         if (rb0 + u >= d.R) break;
-        dst[first + (uint64_t)(rb0 + u) * half_w] = v[u];
+        if (dst) dst[first + (uint64_t)(rb0 + u) * half_w] = v[u];
         c0 += __popc(v[u].x) + __popc(v[u].y);
         c1 += __popc(v[u].z) + __popc(v[u].w);
       }
@@ -241,9 +255,8 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
                                                         double* eps, int32_t* zmax, uint32_t* hcnt,
                                                         uint16_t* hot, double x, int rule,
                                                         cbaa_restore_stats* stats,
-                                                        const uint64_t* __restrict__ cube,
-                                                        uint64_t* hcol, uint32_t gcap,
-                                                        uint32_t* gfit) {
+                                                        CubeSrc cube, uint64_t* hcol,
+                                                        uint32_t gcap, uint32_t* gfit) {
   __shared__ uint32_t wave_cnt[kPrepBlock / kWave];
   __shared__ uint16_t s_list[kGatherCap];
   const uint32_t cs = blockIdx.x;
@@ -292,7 +305,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
   if (lead && threadIdx.x == 0) gfit[cs * d.n_ra + i] = fit ? 1u : 0u;
   if (!fit) return;
   // s_list was written before the last barrier; gcap <= kGatherCap
-  const uint64_t* src = cube + (uint64_t)cs * d.R * d.W + d.aoff[i];
+  const uint64_t src = (uint64_t)cs * d.R * d.W + d.aoff[i];   // word index in the cube
   uint64_t* dst = hcol + ((uint64_t)cs * d.n_ra + i) * gcap * d.R;
   const uint32_t n = base * d.R;
   const uint32_t stride = gridDim.z * blockDim.x;
@@ -305,7 +318,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
     for (int u = 0; u < U; ++u) {
       const uint32_t jj = j + u * stride;
       const uint32_t rb = jj / base, pos = jj - rb * base;
-      v[u] = src[(uint64_t)rb * d.W + s_list[pos]];
+      v[u] = cube_word(cube, src + (uint64_t)rb * d.W + s_list[pos]);
       at[u] = pos * d.R + rb;
     }
 #pragma unroll
@@ -313,7 +326,7 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
   }
   for (; j < n; j += stride) {
     const uint32_t rb = j / base, pos = j - rb * base;
-    dst[pos * d.R + rb] = src[(uint64_t)rb * d.W + s_list[pos]];
+    dst[pos * d.R + rb] = cube_word(cube, src + (uint64_t)rb * d.W + s_list[pos]);
   }
 }
 
@@ -363,6 +376,16 @@ __device__ inline void load_col(const Dims& d, const uint64_t* __restrict__ cube
 }
 
 template <int RPL>
+__device__ inline void load_col(const Dims& d, const CubeSrc& cube, uint32_t cs, uint32_t slot,
+                                Col<RPL>& c) {
+#pragma unroll
+  for (int q = 0; q < RPL; ++q) {
+    const uint32_t rb = lane_id() + q * kWave;
+    c.w[q] = rb < d.R ? cube_word(cube, ((uint64_t)cs * d.R + rb) * d.W + slot) : ~0ull;
+  }
+}
+
+template <int RPL>
 __device__ inline void and_col(Col<RPL>& a, const Col<RPL>& b) {
 #pragma unroll
   for (int r = 0; r < RPL; ++r) a.w[r] &= b.w[r];
@@ -380,7 +403,7 @@ __device__ inline uint32_t col_zeros(const Dims& d, const Col<RPL>& c) {
 }
 
 struct JoinArgs {
-  const uint64_t* cube;
+  CubeSrc cube;
   const uint16_t* zeros;  // [S][W] per-column zero counts of the scan
   const uint16_t* hot;
   const uint64_t* hcol;   // gathered hot columns ([S][n_ra][gcap][R])
@@ -1174,7 +1197,7 @@ namespace {
 
 // Everything after the column scan: thresholds, hot lists and gather, join,
 // ordering.
-int restore_after_scan(const Dims& d, const uint64_t* cube, double x, int rule,
+int restore_after_scan(const Dims& d, const CubeSrc& cube, double x, int rule,
                        const RestoreScratch& rs, uint64_t capacity, cbaa_host* out,
                        cbaa_restore_stats* stats, hipStream_t s) {
   int rc;
@@ -1218,13 +1241,20 @@ int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void
   RestoreScratch rs = carve(d, scratch, capacity);
   int rc = run_scan(d, cube, rs.zeros, rs.ones, stats, s);
   if (rc != CBAA_OK) return rc;
-  return restore_after_scan(d, cube, x, rule, rs, capacity, out, stats, s);
+  CubeSrc one{};
+  one.p[0] = cube;
+  one.k = 1;
+  return restore_after_scan(d, one, x, rule, rs, capacity, out, stats, s);
 }
 
 int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
                          double x, int rule, void* scratch, uint64_t capacity, cbaa_host* out,
                          cbaa_restore_stats* stats, hipStream_t s) {
   if (k > kMergeScanSources) {   // merge in passes first, then the plain restore
+    if (!dst) {
+      set_error("more than %d source cubes need a destination cube", kMergeScanSources);
+      return CBAA_EINVAL;
+    }
     const int rc = launch_merge_or(d, dst, srcs, k, s);
     if (rc != CBAA_OK) return rc;
     return launch_restore(d, dst, x, rule, scratch, capacity, out, stats, s);
@@ -1240,7 +1270,15 @@ int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* sr
   hipLaunchKernelGGL(k_merge_scan, grid, dim3(kScanBlock), 0, s, d, ms, k, (uint4*)dst,
                      (uint32_t*)rs.zeros, rs.ones);
   if ((rc = check_launch("merge scan launch")) != CBAA_OK) return rc;
-  return restore_after_scan(d, dst, x, rule, rs, capacity, out, stats, s);
+  CubeSrc cs{};
+  if (dst) {
+    cs.p[0] = dst;
+    cs.k = 1;
+  } else {   // the merge is not stored: later reads OR the sources
+    for (int j = 0; j < k; ++j) cs.p[j] = srcs[j];
+    cs.k = k;
+  }
+  return restore_after_scan(d, cs, x, rule, rs, capacity, out, stats, s);
 }
 
 int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
@@ -1251,8 +1289,8 @@ int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, 
   if (rc != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, 1), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
                      rs.eps, rs.zmax, rs.hcnt, (uint16_t*)nullptr, 1.0, CBAA_THR_THM2,
-                     (cbaa_restore_stats*)nullptr, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                     0u, (uint32_t*)nullptr);
+                     (cbaa_restore_stats*)nullptr, CubeSrc{}, (uint64_t*)nullptr, 0u,
+                     (uint32_t*)nullptr);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
   return run_est(d, cube, hosts, n, rs.eps, est, zeros, layer_zeros, s);
 }
@@ -1264,8 +1302,8 @@ int launch_features(const Dims& d, const uint64_t* cube, const uint32_t* hosts, 
   if (rc != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, 1), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
                      rs.eps, rs.zmax, rs.hcnt, (uint16_t*)nullptr, 1.0, CBAA_THR_THM2,
-                     (cbaa_restore_stats*)nullptr, (const uint64_t*)nullptr, (uint64_t*)nullptr,
-                     0u, (uint32_t*)nullptr);
+                     (cbaa_restore_stats*)nullptr, CubeSrc{}, (uint64_t*)nullptr, 0u,
+                     (uint32_t*)nullptr);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
   if (F == d.A + 4) {
     hipLaunchKernelGGL(k_row_ones, dim3(d.S * d.R), dim3(kRowBlock), 0, s, d, cube, rs.rows);

@@ -355,6 +355,62 @@ def test_merge_restore_equals_merge_then_restore(cb, k, alias):
     _assert_hosts_equal(got2, got)
 
 
+def _merge_restore(cb, p, dst, srcs, cap=4096):
+    import torch
+    rs = cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, cap))
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    st = cb.stats_tensor()
+    cb.cbaa_merge_restore(p, dst, srcs, 1024.0, cb.THR_THM2, rs, out, cap, st)
+    torch.cuda.synchronize()
+    return cb.host_list(out, int(st[0])), st.cpu().numpy().copy()
+
+
+@pytest.mark.parametrize("k", [1, 2, 5, 16])
+def test_merge_restore_without_destination(cb, k):
+    """With no destination the merged cube is not stored and the restore reads
+    every column it needs as the OR of the router cubes: the host list and the
+    restore counters are those of the stored case, and the oracle's hosts."""
+    p = default_params()
+    t = tracegen.window_small(8)
+    parts = tracegen.split_routers(t.pairs, k, seed=8)
+    srcs = [_gpu_cube(cb, p, q, 0) for q in parts]
+    _say("merge restore, no destination", k)
+    got, st = _merge_restore(cb, p, None, srcs)
+    ref, st_ref = _merge_restore(cb, p, cb.new_cube(p, init=False), srcs)
+    assert np.array_equal(st, st_ref)
+    _assert_hosts_equal(got, ref)
+    want, _ = O.restore(p, O.cube_of(p, t.pairs, 0), 1024.0)
+    _assert_hosts_equal(got, want)
+
+
+def test_merge_restore_without_destination_long_hot_list(cb):
+    """The long-hot-list cube (a list too long for the gather buffer, so the
+    join reads cube columns directly) split over three router cubes: with no
+    destination those direct reads OR the three sources."""
+    p = default_params()
+    t = tracegen.window_small(2)
+    cube_np = O.cube_of(p, t.pairs, 0).copy()
+    _set_columns(p, cube_np, 3, 0, np.arange(1000, 2500))
+    rng = np.random.default_rng(3)
+    who = rng.integers(0, 3, cube_np.size)   # every word of the cube goes to one router
+    srcs = [_cube_from_numpy(np.where(who == i, cube_np, np.uint64(0))) for i in range(3)]
+    _say("merge restore, no destination, long hot list")
+    got, st = _merge_restore(cb, p, None, srcs)
+    want, wst = O.restore(p, cube_np, 1024.0)
+    assert st[1] == wst["hot_columns"] and wst["hot_columns"] > 1500
+    _assert_hosts_equal(got, want)
+
+
+def test_merge_restore_without_destination_needs_at_most_16_sources(cb):
+    p = default_params()
+    srcs = [cb.new_cube(p) for _ in range(17)]
+    import torch
+    rs = cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, 16))
+    out = torch.empty(16 * 16, dtype=torch.uint8, device="cuda")
+    with pytest.raises(RuntimeError, match="16 source cubes"):
+        cb.cbaa_merge_restore(p, None, srcs, 1024.0, cb.THR_THM2, rs, out, 16, cb.stats_tensor())
+
+
 # ---------------------------------------------------------------- estimate
 
 def test_estimate_matches_oracle(cb):
