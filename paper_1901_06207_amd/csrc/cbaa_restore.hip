@@ -514,6 +514,7 @@ struct Walk {
   uint32_t cnt[NRA];                 // |HC(i)|
   const uint16_t* list[NRA];         // HC(i) in ascending order
   uint32_t reg[NRA][kListRegs];      // HC(i)[lane + 64 k], k < kListRegs
+  uint32_t b1_lo, b1_hi;             // this item's window of HC(1) positions
   uint32_t t[NRA];                   // columns of the tuple being extended
   uint32_t tp[NRA];                  // their positions in HC(i)
   uint32_t qc[Q][NRA];               // queued complete tuples in slots
@@ -527,6 +528,7 @@ struct Walk {
 // called with entry base + lane of the list. The first kListRegs rounds take
 // their entries from registers (shifted down one round at a time, so no
 // register is ever picked by a run-time index), later rounds from memory.
+// HC(1) is screened only inside the item's window [b1_lo, b1_hi).
 template <int NRA, int RPL, int LEVEL, typename F>
 __device__ __attribute__((always_inline)) void for_list(const Walk<NRA, RPL>& w, F&& round) {
   uint32_t r[kListRegs];
@@ -541,8 +543,11 @@ __device__ __attribute__((always_inline)) void for_list(const Walk<NRA, RPL>& w,
 #pragma unroll
       for (int k = 0; k + 1 < kListRegs; ++k) r[k] = r[k + 1];
     } else {
+      if (LEVEL == 1 && base < w.b1_lo) continue;
       cand = j < cnt ? w.list[LEVEL][j] : 0u;
     }
+    if (LEVEL == 1 && base >= w.b1_hi) break;
+    if (LEVEL == 1 && base < w.b1_lo) continue;
     round(cand, j < cnt, base);
   }
 }
@@ -704,21 +709,29 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
 template <int NRA, int NVA, int RPL>
 __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
   __shared__ uint32_t pre[257];
+  __shared__ uint32_t s_rounds;
   // hot columns come from the gathered copy only if every list fit it
   uint32_t missed = 0;
   for (uint32_t i = lane_id(); i < d.S * NRA; i += kWave) missed |= ja.gfit[i] ^ 1u;
   const bool all_fit = __ballot(missed != 0) == 0;
-  // prefix over sketches of |HC(0)|: flattened work list of (cs, hc0)
+  // Work items: (window of 64 positions of HC(1), cs, hc0), the window
+  // outermost, so that the windows of one hc0 fall to different waves: a hot
+  // column of RA 0 that extends to many tuples is spread over several waves.
+  // pre: prefix over sketches of |HC(0)|; s_rounds: most windows of any HC(1).
   if (threadIdx.x == 0) {
-    uint32_t acc = 0;
+    uint32_t acc = 0, rounds = 0;
     for (uint32_t cs = 0; cs < d.S; ++cs) {
       pre[cs] = acc;
       acc += ja.hcnt[cs * NRA + 0];
+      const uint32_t r1 = (ja.hcnt[cs * NRA + 1] + kWave - 1) / kWave;
+      rounds = r1 > rounds ? r1 : rounds;
     }
     pre[d.S] = acc;
+    s_rounds = rounds;
   }
   __syncthreads();
-  const uint32_t total = pre[d.S];
+  const uint32_t total0 = pre[d.S];
+  const uint32_t total = total0 * s_rounds;
   const uint32_t waves_per_block = kJoinBlock / kWave;
   const uint32_t gw = blockIdx.x * waves_per_block + threadIdx.x / kWave;
   const uint32_t nwaves = gridDim.x * waves_per_block;
@@ -728,19 +741,23 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
   w.n_tuples = 0;
   w.found.n = 0;
   for (uint32_t item = gw; item < total; item += nwaves) {
-    uint32_t lo = 0, hi = d.S;  // largest cs with pre[cs] <= item
+    const uint32_t win = item / total0, flat = item - win * total0;
+    uint32_t lo = 0, hi = d.S;  // largest cs with pre[cs] <= flat
     while (hi - lo > 1) {
       const uint32_t mid = (lo + hi) / 2;
-      if (pre[mid] <= item) lo = mid; else hi = mid;
+      if (pre[mid] <= flat) lo = mid; else hi = mid;
     }
     w.cs = lo;
-    const uint32_t pos0 = item - pre[w.cs];
-    w.zm = ja.zmax[w.cs];
 #pragma unroll
     for (int i = 0; i < NRA; ++i) {
       w.cnt[i] = ja.hcnt[w.cs * NRA + i];
       w.list[i] = ja.hot + ((uint64_t)w.cs * NRA + i) * d.maxc_ra;
     }
+    w.b1_lo = win * kWave;
+    w.b1_hi = w.b1_lo + kWave;
+    if (w.b1_lo >= w.cnt[1]) continue;   // this sketch's HC(1) has fewer windows
+    const uint32_t pos0 = flat - pre[w.cs];
+    w.zm = ja.zmax[w.cs];
     w.t[0] = w.list[0][pos0];
     w.tp[0] = pos0;
 #pragma unroll
