@@ -172,8 +172,11 @@ struct CubeSrc {
 };
 
 __device__ inline uint64_t cube_word(const CubeSrc& c, uint64_t i) {
-  uint64_t v = c.p[0][i];
-  for (int j = 1; j < c.k; ++j) v |= c.p[j][i];
+  // the first two sources are read with no branch between them (one cube:
+  // the same word twice), so both loads are in flight together
+  const uint64_t* p1 = c.k > 1 ? c.p[1] : c.p[0];
+  uint64_t v = c.p[0][i] | p1[i];
+  for (int j = 2; j < c.k; ++j) v |= c.p[j][i];
   return v;
 }
 
@@ -475,12 +478,13 @@ __device__ inline void emit_host(const Dims& d, const JoinArgs& ja, Found& f, ui
 }
 
 // Column `col` at position `pos` of the hot list of RA `level` in sketch cs:
-// from the gathered copy when every list of the restore fit the gather
-// buffer (`gathered`, uniform over the grid), else straight from the cube.
-template <int RPL>
-__device__ inline void load_hot(const Dims& d, const JoinArgs& ja, bool gathered, uint32_t cs,
-                                uint32_t level, uint32_t pos, uint32_t col, Col<RPL>& c) {
-  if (gathered) {
+// from the gathered copy (G: every list of the restore fit the gather
+// buffer) or straight from the cube. G is a compile-time choice so that a
+// batch's loads have no branch between them and are in flight together.
+template <int RPL, bool G>
+__device__ inline void load_hot(const Dims& d, const JoinArgs& ja, uint32_t cs, uint32_t level,
+                                uint32_t pos, uint32_t col, Col<RPL>& c) {
+  if constexpr (G) {
     const uint64_t* src = ja.hcol + (((uint64_t)cs * d.n_ra + level) * ja.gcap + pos) * d.R;
 #pragma unroll
     for (int q = 0; q < RPL; ++q) {
@@ -509,7 +513,6 @@ struct Walk {
   static constexpr int Q = QueueLen<RPL>::value;
   uint32_t cs;
   int32_t zm;
-  bool gathered;                     // hot columns read from the gathered copy
   Col<RPL> c0;                       // column hc0, whole
   uint32_t cnt[NRA];                 // |HC(i)|
   const uint16_t* list[NRA];         // HC(i) in ascending order
@@ -554,19 +557,27 @@ __device__ __attribute__((always_inline)) void for_list(const Walk<NRA, RPL>& w,
 
 // Checks every queued tuple: AND of its RA columns with hc0, the VA
 // zero-count test, the VA columns, the count against Zmax, the output.
-template <int NRA, int NVA, int RPL>
+template <int NRA, int NVA, int RPL, bool G>
 __device__ __attribute__((always_inline)) void check_queue(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w) {
   constexpr int Q = Walk<NRA, RPL>::Q;
   Col<RPL> acc[Q];
   uint32_t lp[Q];
   int32_t zva[Q];
+  // every slot is loaded, the empty ones (q >= nq) repeating slot 0, so that
+  // no branch separates the loads
 #pragma unroll
   for (int q = 0; q < Q; ++q) {
-    if (q >= w.nq) break;
+    const bool live = q < w.nq;
+    uint32_t col[NRA], pos[NRA];
+#pragma unroll
+    for (int i = 1; i < NRA; ++i) {
+      col[i] = live ? w.qc[q][i] : w.qc[0][i];
+      pos[i] = live ? w.qp[q][i] : w.qp[0][i];
+    }
     // LP = concatenation of the EPs
     uint32_t x = rotl_in(w.t[0] & low_mask(d.ep[0]), d.off[0], d.L);
 #pragma unroll
-    for (int i = 1; i < NRA; ++i) x |= rotl_in(w.qc[q][i] & low_mask(d.ep[i]), d.off[i], d.L);
+    for (int i = 1; i < NRA; ++i) x |= rotl_in(col[i] & low_mask(d.ep[i]), d.off[i], d.L);
     lp[q] = x;
     int32_t z = 0;
 #pragma unroll
@@ -579,7 +590,7 @@ __device__ __attribute__((always_inline)) void check_queue(const Dims& d, const 
 #pragma unroll
     for (int i = 1; i < NRA; ++i) {
       Col<RPL> c;
-      load_hot<RPL>(d, ja, w.gathered, w.cs, i, w.qp[q][i], w.qc[q][i], c);
+      load_hot<RPL, G>(d, ja, w.cs, i, pos[i], col[i], c);
       and_col(acc[q], c);
     }
   }
@@ -608,7 +619,7 @@ __device__ __attribute__((always_inline)) void check_queue(const Dims& d, const 
 }
 
 // Last RA: every CP-valid candidate completes a tuple, which is queued.
-template <int NRA, int NVA, int RPL>
+template <int NRA, int NVA, int RPL, bool G>
 __device__ __attribute__((always_inline)) void extend_last(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w) {
   constexpr int L = NRA - 1;
   constexpr int Q = Walk<NRA, RPL>::Q;
@@ -639,14 +650,14 @@ __device__ __attribute__((always_inline)) void extend_last(const Dims& d, const 
       }
       w.qc[0][L] = h;
       w.qp[0][L] = base + (uint32_t)l;
-      if (++w.nq == Q) check_queue<NRA, NVA, RPL>(d, ja, w);
+      if (++w.nq == Q) check_queue<NRA, NVA, RPL, G>(d, ja, w);
     }
   });
 }
 
 // Intermediate RA LEVEL (0 < LEVEL < NRA - 1): CP screen against hc_{l-1},
 // then the AND with the prefix `acc`, pruned above Zmax.
-template <int NRA, int NVA, int RPL, int LEVEL>
+template <int NRA, int NVA, int RPL, int LEVEL, bool G>
 __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w,
                        const Col<RPL>& acc) {
   const uint32_t want_lo = w.t[LEVEL - 1] >> d.ep[LEVEL - 1];
@@ -669,10 +680,15 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
           nb = q + 1;
         }
       }
+      // unused slots repeat slot 0, so the loads have no branch between them
+#pragma unroll
+      for (int q = 1; q < kBatch; ++q) {
+        h[q] = q < nb ? h[q] : h[0];
+        pos[q] = q < nb ? pos[q] : pos[0];
+      }
       Col<RPL> c[kBatch];
 #pragma unroll
-      for (int q = 0; q < kBatch; ++q)
-        if (q < nb) load_hot<RPL>(d, ja, w.gathered, w.cs, LEVEL, pos[q], h[q], c[q]);
+      for (int q = 0; q < kBatch; ++q) load_hot<RPL, G>(d, ja, w.cs, LEVEL, pos[q], h[q], c[q]);
       uint32_t keep = 0;   // candidates whose partial AND is within Zmax
 #pragma unroll
       for (int q = 0; q < kBatch; ++q) {
@@ -690,9 +706,9 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
           w.t[LEVEL] = h[0];
           w.tp[LEVEL] = pos[0];
           if constexpr (LEVEL + 1 < NRA - 1)
-            extend<NRA, NVA, RPL, LEVEL + 1>(d, ja, w, c[0]);
+            extend<NRA, NVA, RPL, LEVEL + 1, G>(d, ja, w, c[0]);
           else
-            extend_last<NRA, NVA, RPL>(d, ja, w);
+            extend_last<NRA, NVA, RPL, G>(d, ja, w);
         }
         keep >>= 1;
 #pragma unroll
@@ -704,6 +720,51 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
       }
     }
   });
+}
+
+// The items of one wave (gw, gw + nwaves, ...) with hot columns read from
+// the gathered copy (G) or from the cube.
+template <int NRA, int NVA, int RPL, bool G>
+__device__ __attribute__((always_inline)) void join_items(const Dims& d, const JoinArgs& ja,
+                                                          Walk<NRA, RPL>& w, const uint32_t* pre,
+                                                          uint32_t total0, uint32_t total,
+                                                          uint32_t gw, uint32_t nwaves) {
+  for (uint32_t item = gw; item < total; item += nwaves) {
+    const uint32_t win = item / total0, flat = item - win * total0;
+    uint32_t lo = 0, hi = d.S;  // largest cs with pre[cs] <= flat
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) / 2;
+      if (pre[mid] <= flat) lo = mid; else hi = mid;
+    }
+    w.cs = lo;
+#pragma unroll
+    for (int i = 0; i < NRA; ++i) {
+      w.cnt[i] = ja.hcnt[w.cs * NRA + i];
+      w.list[i] = ja.hot + ((uint64_t)w.cs * NRA + i) * d.maxc_ra;
+    }
+    w.b1_lo = win * kWave;
+    w.b1_hi = w.b1_lo + kWave;
+    if (w.b1_lo >= w.cnt[1]) continue;   // this sketch's HC(1) has fewer windows
+    const uint32_t pos0 = flat - pre[w.cs];
+    w.zm = ja.zmax[w.cs];
+    w.t[0] = w.list[0][pos0];
+    w.tp[0] = pos0;
+#pragma unroll
+    for (int i = 1; i < NRA; ++i) {
+#pragma unroll
+      for (int k = 0; k < kListRegs; ++k) {
+        const uint32_t j = (uint32_t)k * kWave + lane_id();
+        w.reg[i][k] = j < w.cnt[i] ? w.list[i][j] : 0u;
+      }
+    }
+    load_hot<RPL, G>(d, ja, w.cs, 0, pos0, w.t[0], w.c0);
+    w.nq = 0;
+    if constexpr (NRA > 2)
+      extend<NRA, NVA, RPL, 1, G>(d, ja, w, w.c0);
+    else
+      extend_last<NRA, NVA, RPL, G>(d, ja, w);
+    if (w.nq) check_queue<NRA, NVA, RPL, G>(d, ja, w);
+  }
 }
 
 template <int NRA, int NVA, int RPL>
@@ -736,46 +797,13 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
   const uint32_t gw = blockIdx.x * waves_per_block + threadIdx.x / kWave;
   const uint32_t nwaves = gridDim.x * waves_per_block;
   Walk<NRA, RPL> w;
-  w.gathered = all_fit;
   w.n_partial = 0;
   w.n_tuples = 0;
   w.found.n = 0;
-  for (uint32_t item = gw; item < total; item += nwaves) {
-    const uint32_t win = item / total0, flat = item - win * total0;
-    uint32_t lo = 0, hi = d.S;  // largest cs with pre[cs] <= flat
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) / 2;
-      if (pre[mid] <= flat) lo = mid; else hi = mid;
-    }
-    w.cs = lo;
-#pragma unroll
-    for (int i = 0; i < NRA; ++i) {
-      w.cnt[i] = ja.hcnt[w.cs * NRA + i];
-      w.list[i] = ja.hot + ((uint64_t)w.cs * NRA + i) * d.maxc_ra;
-    }
-    w.b1_lo = win * kWave;
-    w.b1_hi = w.b1_lo + kWave;
-    if (w.b1_lo >= w.cnt[1]) continue;   // this sketch's HC(1) has fewer windows
-    const uint32_t pos0 = flat - pre[w.cs];
-    w.zm = ja.zmax[w.cs];
-    w.t[0] = w.list[0][pos0];
-    w.tp[0] = pos0;
-#pragma unroll
-    for (int i = 1; i < NRA; ++i) {
-#pragma unroll
-      for (int k = 0; k < kListRegs; ++k) {
-        const uint32_t j = (uint32_t)k * kWave + lane_id();
-        w.reg[i][k] = j < w.cnt[i] ? w.list[i][j] : 0u;
-      }
-    }
-    load_hot<RPL>(d, ja, w.gathered, w.cs, 0, pos0, w.t[0], w.c0);
-    w.nq = 0;
-    if constexpr (NRA > 2)
-      extend<NRA, NVA, RPL, 1>(d, ja, w, w.c0);
-    else
-      extend_last<NRA, NVA, RPL>(d, ja, w);
-    if (w.nq) check_queue<NRA, NVA, RPL>(d, ja, w);
-  }
+  if (all_fit)
+    join_items<NRA, NVA, RPL, true>(d, ja, w, pre, total0, total, gw, nwaves);
+  else
+    join_items<NRA, NVA, RPL, false>(d, ja, w, pre, total0, total, gw, nwaves);
   if (lane_id() < w.found.n)
     ja.wbuf[(uint64_t)gw * kWave + lane_id()] = make_host(d, ja, w.found.cs, w.found.lp, w.found.z);
   if (lane_id() == 0) ja.wcnt[gw] = w.found.n;
