@@ -137,11 +137,15 @@ def main():
     capacity = 1 << 14
     rs_bytes = cbaa.cbaa_restore_scratch_bytes(cfg, capacity)
     scratch_r = [cbaa.scratch_tensor(rs_bytes, dev) for _ in range(2)]
-    outs = [torch.empty(capacity * cbaa.HOST_BYTES, dtype=torch.uint8, device=dev) for _ in range(2)]
-    stats = [cbaa.stats_tensor(dev) for _ in range(2)]
-    h_outs = [torch.empty(capacity * cbaa.HOST_BYTES, dtype=torch.uint8, pin_memory=True)
-              for _ in range(2)]
-    h_stats = [torch.empty(4, dtype=torch.int64, pin_memory=True) for _ in range(2)]
+    # both sides' lists and counters in one device buffer, so that the step
+    # brings its results to the host with one copy: [list 0 | list 1 | stats]
+    lb = capacity * cbaa.HOST_BYTES
+    d_res = torch.empty(2 * lb + 2 * 32, dtype=torch.uint8, device=dev)
+    h_res = torch.empty(2 * lb + 2 * 32, dtype=torch.uint8, pin_memory=True)
+    outs = [d_res[i * lb:(i + 1) * lb] for i in range(2)]
+    stats = [d_res[2 * lb + 32 * i: 2 * lb + 32 * (i + 1)].view(torch.int64) for i in range(2)]
+    h_outs = [h_res[i * lb:(i + 1) * lb] for i in range(2)]
+    h_stats = [h_res[2 * lb + 32 * i: 2 * lb + 32 * (i + 1)].view(torch.int64) for i in range(2)]
 
     ev = {}
 
@@ -167,9 +171,7 @@ def main():
         if timed:
             mark("copy", stream)
         with torch.cuda.stream(stream):
-            for i in range(2):
-                h_stats[i].copy_(stats[i], non_blocking=True)
-                h_outs[i].copy_(outs[i], non_blocking=True)
+            h_res.copy_(d_res, non_blocking=True)
         if timed:
             mark("end", stream)
 
