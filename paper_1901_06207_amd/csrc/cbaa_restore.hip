@@ -345,8 +345,10 @@ __global__ void k_reset(cbaa_restore_stats* st, uint32_t* ones, uint32_t n_ones)
 
 // ---- tuple join and union-column verification (Alg. 3) ------------------
 //
-// One wave owns one hot column hc0 of RA 0 and walks the tuples that extend
-// it, RA by RA: candidates of RA l are screened 64 at a time by the CP check
+// A wave takes work items, each a hot column hc0 of RA 0 with one 64-entry
+// window of the RA 1 hot list, and walks the tuples that extend hc0 through
+// that window, RA by RA: candidates of RA l are screened 64 at a time by the
+// CP check
 // of Alg. 3 against hc_{l-1} (and, for the last RA, against hc_0), then the
 // AND of the columns chosen so far is counted. Because AND can only add zero
 // bits, a partial tuple whose AND already has more than Zmax zeros cannot
@@ -361,6 +363,8 @@ __global__ void k_reset(cbaa_restore_stats* st, uint32_t* ones, uint32_t n_ones)
 //   and a full queue is checked at once: the columns of all its tuples and the
 //   scan's zero counts of their VA columns are loaded together, then the VA
 //   columns of the tuples that pass;
+// * the column loads of a candidate batch or of a queue have no branch
+//   between them, so they are in flight together;
 // * counts over the wave are summed with DPP row shifts, not LDS permutes.
 
 template <int RPL>
