@@ -248,8 +248,15 @@ def test_restore_capacity_overflow_and_empty(cb):
     cb.cbaa_restore(p, cube, 1024.0, 0, scratch, out, 8, st)
     torch.cuda.synchronize()
     assert int(st[0]) > 8
+    cut = cb.host_list(out, 8)
     full, _ = cb.restore(p, cube, 1024.0, capacity=8)   # grows and retries
     assert full.size == int(st[0])
+    # a cut output: 8 distinct hosts of the full list, in ascending IP order
+    assert np.all(np.diff(cut["ip"].astype(np.int64)) > 0)
+    rows = {int(h["ip"]): h for h in full}
+    for h in cut:
+        ref = rows[int(h["ip"])]
+        assert (h["zeros"], h["cs"], h["flags"]) == (ref["zeros"], ref["cs"], ref["flags"])
     empty, est = cb.restore(p, cb.new_cube(p), 1024.0)
     assert empty.size == 0 and est["hot_columns"] == 0
     # capacity 0: counts only
