@@ -43,7 +43,7 @@ HBM_PEAK_GBS = 8000.0
 # tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
 # valid only while the update kernels' sources are the ones measured
 # (profiles/update_core_edge_64M_traffic.txt).
-UPDATE_TRAFFIC = {"bytes": 4047753478, "sources": {
+UPDATE_TRAFFIC = {"bytes": 4051983283, "sources": {
     "paper_1901_06207_amd/csrc/cbaa_partition.hip":
         "cdb6598fcf7d5dc52bbe9fc10881a540339c4a818082b21ec0e80bb94eedd4e0",
     "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
