@@ -343,6 +343,15 @@ def main():
             "restore_ms_p99": round(float(np.percentile(restore_ms, 99)), 4),
             "lists_to_host_ms": round(float(copy_ms.mean()), 4),
             "restore_scan": scan,
+            # the whole window end of one side against the HBM roofline: its
+            # algorithmic bytes are the router cubes read once (plus the merged
+            # cube written once when it is stored)
+            "window_end_roofline": {
+                "alg_bytes": int((len(parts) + (1 if args.store_merged else 0)) * cube_bytes),
+                "achieved_gbs": round((len(parts) + (1 if args.store_merged else 0)) * cube_bytes
+                                      / (float(window_end_ms.mean()) * 1e-3) / 1e9, 1),
+                "frac": round((len(parts) + (1 if args.store_merged else 0)) * cube_bytes
+                              / (float(window_end_ms.mean()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "super_hosts": {"source_keyed": n_found[0], "destination_keyed": n_found[1]},
         },
         "roofline": roofline,
