@@ -61,3 +61,32 @@ def test_adam_matches_torch():
         opt.step()
         w, m, v = M.adam_step(w, g, m, v, step, 1e-2)
         assert np.allclose(w, p.detach().numpy(), rtol=1e-12, atol=1e-12)
+
+
+def test_features_hand_values():
+    """Feature values worked by hand at g = 4096 (each is ln(1 + g u) with u
+    the log ratio of the column's zeros to its no-sharing expectation):
+    z = g gives u = 0; z = g/2 gives u = ln 2, so ln(1 + 4096 ln 2) =
+    7.951605...; z = g/4 gives ln(1 + 4096 ln 4) = 8.644576...; z = 0 is read
+    as one zero, ln(1 + 4096 ln 4096) = 10.436189.... The union column's count
+    divides by g - g eps (Thm. 2): with eps = 1/4, Z = 3072 is exactly the
+    expected shared fill (u = 0), Z = 1536 gives ln 2 again, and Z above
+    g - g eps is clamped to 0 rather than going negative; g eps = 1024. The
+    row-aware pair divides by g - shared instead."""
+    layer = np.array([[4096, 2048, 1024, 0]] * 3, np.uint16)
+    union = np.array([3072, 1536, 4096], np.uint16)
+    eps = np.full(3, 0.25)
+    shared = np.array([1024.0, 2048.0, 0.0])
+    x = M.features(layer, union, eps, 4096, extended=True, shared=shared)
+    assert x.dtype == np.float32 and x.shape == (3, 8)
+    per = np.array([0.0, 7.951605404591579, 8.64457652142652, 10.436189247200675], np.float32)
+    for k in range(3):
+        assert np.allclose(x[k, :4], per, rtol=1e-6, atol=0)
+    assert np.allclose(x[:, 4], [0.0, 7.951605404591579, 0.0], rtol=1e-6, atol=0)
+    assert np.all(x[:, 5] == 1024.0)
+    # row-aware: Z = 3072 against g - 1024 = 3072 -> 0; Z = 1536 against
+    # g - 2048 = 2048 -> ln(1 + 4096 ln(4/3)); Z = 4096 against g -> 0
+    assert np.allclose(x[:, 6], [0.0, np.log1p(4096 * np.log(4 / 3)), 0.0], rtol=1e-6, atol=0)
+    assert np.array_equal(x[:, 7], shared.astype(np.float32))
+    base = M.features(layer, union, eps, 4096, extended=False)
+    assert base.shape == (3, 4) and np.array_equal(base, x[:, :4])

@@ -497,3 +497,126 @@ def test_detection_rates_definitions():
     assert r["fnr"] == pytest.approx(1 / 3)     # host 1 missed
     assert r["fpr"] == pytest.approx(2 / 3)     # hosts 4 and 9 below theta
     assert r["ftr"] == pytest.approx(1.0)
+
+
+# ---------------------------------------------------------------- thresholds at eps > 0
+
+def test_threshold_closed_form_with_sharing():
+    """Both rules at eps > 0 against values worked by hand (golden file):
+    array fills are powers of two, so eps is exact and each floor is far from
+    an integer boundary."""
+    gold = _golden("threshold_eps_pos.json")
+    for case in gold["cases"]:
+        p = dict(default_params(), log2_g=case["log2_g"])
+        g, A = 1 << p["log2_g"], p["n_ra"] + p["n_va"]
+        S = 1 << p["r"]
+        ones = np.array([[num * (1 << p["cbn"][a]) * g // den for a, (num, den)
+                          in enumerate(case["fills"])]] * S, np.uint32).ravel()
+        assert ones.size == S * A
+        for rule, key in ((O.THR_THM2, "thm2"), (O.THR_PAPER, "paper")):
+            eps, zmax = O.thresholds(p, ones, case["theta"], rule)
+            assert np.all(eps == case["eps"]), (case, rule)
+            assert np.all(zmax == case[key]), (case, rule, zmax[0])
+        assert case["thm2"] == math.floor(case["thm2_real"])
+        assert case["paper"] == math.floor(case["paper_real"])
+
+
+def _filled_cube(p, fills, seed):
+    """A cube whose array a has each bit set with probability fills[a]
+    (a power of two: the AND of k random words has density 2^-k)."""
+    rng = np.random.default_rng(seed)
+    g, A, ncol, W, aoff = _layout(p)
+    S, R = 1 << p["r"], g // 64
+    cube = np.zeros((S, R, W), np.uint64)
+    for a, f in enumerate(fills):
+        k = int(round(-math.log2(f)))
+        w = np.full((S, R, ncol[a]), np.uint64(0xFFFFFFFFFFFFFFFF))
+        for _ in range(k):
+            w &= rng.integers(0, 1 << 64, (S, R, ncol[a]), dtype=np.uint64)
+        cube[:, :, aoff[a]:aoff[a] + ncol[a]] = w
+    return cube.ravel()
+
+
+def _set_host_union(p, cube, host, rows):
+    """Overwrite every column of `host` with exactly the bits in `rows`, so
+    its union column (Def. 2) is that set."""
+    g, A, ncol, W, aoff = _layout(p)
+    R = g // 64
+    cs, cols = O.host_columns(p, host)
+    words = np.zeros(R, np.uint64)
+    for b in rows:
+        words[b // 64] |= np.uint64(1) << np.uint64(b % 64)
+    for a in range(A):
+        for rb in range(R):
+            cube[(cs * R + rb) * W + aoff[a] + cols[a]] = words[rb]
+    return cs
+
+
+SHARED_CFG = dict(default_params(), cbn=[10, 10, 10, 10], cl_bs=[4, 14, 24])
+
+
+@pytest.mark.parametrize("fills", [(0.5, 0.5, 0.25, 0.25), (0.5, 0.5, 0.5, 0.5)])
+def test_thm2_threshold_is_estimate_crossing_with_sharing(fills):
+    """Thm. 2 at material sharing (eps = 1/64 and 1/16): for union columns
+    with every zero count around the threshold, the Thm. 2 estimate reaches
+    theta exactly when Z <= Zmax of rule THM2."""
+    p = SHARED_CFG
+    assert O.config_ok(p)
+    g = 1 << p["log2_g"]
+    theta = 1024.0
+    cube = _filled_cube(p, fills, seed=5)
+    host = 0x0A0B0C0D
+    rng = np.random.default_rng(6)
+    seen = set()
+    zmax0 = int(math.floor((g - g * np.prod(fills)) * math.exp(-theta / g)))
+    for z in range(zmax0 - 4, zmax0 + 5):
+        rows = rng.choice(g, g - z, replace=False)
+        cs = _set_host_union(p, cube, host, rows)
+        _, ones = O.column_zeros(p, cube)
+        eps, zmax = O.thresholds(p, ones, theta, O.THR_THM2)
+        assert eps[cs] > 0.5 * np.prod(fills)
+        est, zz, _ = O.estimate(p, cube, np.array([host], np.uint32))
+        assert zz[0] == z
+        assert (est[0] >= theta) == (z <= zmax[cs]), (z, zmax[cs], est[0])
+        seen.add(bool(z <= zmax[cs]))
+    assert seen == {True, False}
+
+
+@pytest.mark.parametrize("fills", [(0.5, 0.5, 0.25, 0.25), (0.5, 0.5, 0.5, 0.5)])
+def test_paper_threshold_is_crossing_of_its_correction(fills):
+    """The printed threshold of Sec. 3.3, Z <= g(1+eps)e^{-theta/g} - g eps,
+    says the same as -g ln((Z + g eps) / (g + g eps)) >= theta. Zmax of rule
+    PAPER must sit exactly where that log form crosses theta."""
+    p = SHARED_CFG
+    g = 1 << p["log2_g"]
+    cube = _filled_cube(p, fills, seed=7)
+    _, ones = O.column_zeros(p, cube)
+    for theta in (256.0, 1024.0, 2048.0):
+        eps, zmax = O.thresholds(p, ones, theta, O.THR_PAPER)
+        for cs in range(1 << p["r"]):
+            e, zm = float(eps[cs]), int(zmax[cs])
+
+            def corrected(z):
+                return -g * math.log((z + g * e) / (g + g * e))
+
+            assert e > 0.5 * np.prod(fills)
+            assert corrected(zm) >= theta > corrected(zm + 1), (cs, theta, zm)
+
+
+# ---------------------------------------------------------------- column statistics
+
+@pytest.mark.parametrize("name", ["default_g64", "g128_r3", "ra4_va2", "hetero_r5"])
+def test_column_zeros_by_unpacking_every_bit(name):
+    """Per-column zero counts and per-array one counts (Alg. 2's inputs)
+    against numpy unpacking every bit of the cube by the layout formula."""
+    p = TINY_CONFIGS[name]
+    g, A, ncol, W, aoff = _layout(p)
+    S, R = 1 << p["r"], g // 64
+    cube = O.cube_of(p, tiny_trace(17).pairs, O.SIDE_SRC)
+    bits = np.unpackbits(cube.view(np.uint8), bitorder="little").reshape(S, R, W, 64)
+    col_ones = bits.sum(axis=(1, 3))                      # [S, W]
+    zeros, ones = O.column_zeros(p, cube)
+    assert np.array_equal(zeros.reshape(S, W), g - col_ones)
+    want_ones = np.stack([col_ones[:, aoff[a]:aoff[a] + ncol[a]].sum(axis=1) for a in range(A)], 1)
+    assert np.array_equal(ones.reshape(S, A), want_ones)
+    assert col_ones.max() > 0 and (g - col_ones).min() < g
