@@ -140,12 +140,13 @@ def main():
     # both sides' lists and counters in one device buffer, so that the step
     # brings its results to the host with one copy: [list 0 | list 1 | stats]
     lb = capacity * cbaa.HOST_BYTES
-    d_res = torch.empty(2 * lb + 2 * 32, dtype=torch.uint8, device=dev)
-    h_res = torch.empty(2 * lb + 2 * 32, dtype=torch.uint8, pin_memory=True)
+    sb = cbaa.STATS_BYTES
+    d_res = torch.empty(2 * lb + 2 * sb, dtype=torch.uint8, device=dev)
+    h_res = torch.empty(2 * lb + 2 * sb, dtype=torch.uint8, pin_memory=True)
     outs = [d_res[i * lb:(i + 1) * lb] for i in range(2)]
-    stats = [d_res[2 * lb + 32 * i: 2 * lb + 32 * (i + 1)].view(torch.int64) for i in range(2)]
+    stats = [d_res[2 * lb + sb * i: 2 * lb + sb * (i + 1)].view(torch.int64) for i in range(2)]
     h_outs = [h_res[i * lb:(i + 1) * lb] for i in range(2)]
-    h_stats = [h_res[2 * lb + 32 * i: 2 * lb + 32 * (i + 1)].view(torch.int64) for i in range(2)]
+    h_stats = [h_res[2 * lb + sb * i: 2 * lb + sb * (i + 1)].view(torch.int64) for i in range(2)]
 
     ev = {}
 
@@ -413,7 +414,7 @@ def bench_batched(cfg, dev, args):
     cap = 1 << 14
     rs = cbaa.scratch_tensor(cbaa.cbaa_restore_scratch_bytes(cfg, cap), dev)
     outs = torch.empty((2 * K, cap * cbaa.HOST_BYTES), dtype=torch.uint8, device=dev)
-    stats = torch.zeros((2 * K, 4), dtype=torch.int64, device=dev)
+    stats = torch.zeros((2 * K, len(cbaa.STATS_FIELDS)), dtype=torch.int64, device=dev)
     ev = {}
 
     def mark(name, st):

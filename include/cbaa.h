@@ -31,7 +31,7 @@
 extern "C" {
 #endif
 
-#define CBAA_ABI_VERSION 1u
+#define CBAA_ABI_VERSION 2u
 #define CBAA_MAX_RA 4
 #define CBAA_MAX_VA 2
 #define CBAA_MAX_ARRAYS (CBAA_MAX_RA + CBAA_MAX_VA)
@@ -59,6 +59,12 @@ extern "C" {
 
 /* Restored host flag: the union column had no zero bit (estimate uses Z = 1). */
 #define CBAA_FLAG_SATURATED 1u
+
+/* Bits of cbaa_restore_stats.status. */
+#define CBAA_STATUS_CONFIG 1u  /* a cube read had no valid header of this configuration:
+                                  nothing was restored (n_hosts = 0) */
+#define CBAA_STATUS_BUDGET 2u  /* the tuple check stopped at its work budget: the list
+                                  holds the hosts found until then, not all of them */
 
 /*
  * Configuration (Sec. 3.1-3.3). Arrays 0..n_ra-1 are restoring arrays (RA),
@@ -106,13 +112,38 @@ typedef struct cbaa_restore_stats {
   uint64_t hot_columns;     /* sum over sketches and RAs of |HC(i)| (Alg. 2) */
   uint64_t partial_checked; /* partial tuples whose AND-ed columns were counted */
   uint64_t tuples_checked;  /* complete CP-valid tuples whose union column was counted */
+  uint64_t tuple_space;     /* sum over sketches of prod_i |HC(i)|: the tuples Alg. 3
+                               enumerates before its CP check (saturates at 2^64 - 1) */
+  uint64_t status;          /* CBAA_STATUS_* bits; 0 = complete */
 } cbaa_restore_stats;
 
-/* Cube memory layout (64-bit little-endian words). Bit b of column `col` of
+/* Cube memory layout. A cube is a 256-byte header followed by the bits.
+ *
+ * Header (Sec. 3.3: only arrays of the same structure are merged; the header
+ * records the structure so that a merge or restore can tell):
+ *   word 0  magic CBAA_CUBE_MAGIC
+ *   word 1  config hash: cbaa_config_hash() of the configuration it was built with
+ *   word 2  bytes of bits after the header
+ *   word 3  low 32 bits CBAA_ABI_VERSION, high 32 bits state: CBAA_CUBE_VALID, or
+ *           CBAA_CUBE_MIXED once bits of another configuration (or of a cube with
+ *           no valid header) have been OR-ed into it
+ *   words 4..31 zero
+ * cbaa_cube_init and fresh batch streams write a valid header; updates and
+ * merges mark their destination MIXED when a source or the destination itself
+ * does not carry this configuration's valid header; restores report such a cube
+ * in cbaa_restore_stats.status and restore nothing from it. These checks run on
+ * the device inside the calls' own launches, so every call stays asynchronous
+ * and capturable; cbaa_cube_check reads a header back synchronously.
+ *
+ * Bits (64-bit little-endian words after the header). Bit b of column `col` of
  * array a in sketch cs is bit (b & 63) of word
  *     ((cs * R + (b >> 6)) * W) + A_off(a) + col
  * where R = g/64, W = sum_a c(a) and A_off(a) = sum_{a' < a} c(a'). A run of
  * W words (one 64-bit row block of every column of one sketch) is contiguous. */
+#define CBAA_HEADER_BYTES 256u
+#define CBAA_CUBE_MAGIC 0x4542554341414243ull /* "CBAACUBE" in little-endian bytes */
+#define CBAA_CUBE_VALID 0u
+#define CBAA_CUBE_MIXED 1u
 
 /* ---- configuration -------------------------------------------------- */
 
@@ -128,9 +159,20 @@ int cbaa_config_default(cbaa_config* h_out);
  * Returns CBAA_OK or CBAA_ECONFIG. */
 int cbaa_config_validate(const cbaa_config* h_cfg);
 
-/* Bytes of one cube: 2^r * g/8 * sum_a c(a) (= 2^27 at the defaults). 0 if
- * the configuration is invalid. */
+/* Bytes of one cube: the 256-byte header plus 2^r * g/8 * sum_a c(a) bytes of
+ * bits (2^27 at the defaults). 0 if the configuration is invalid. */
 uint64_t cbaa_cube_bytes(const cbaa_config* h_cfg);
+
+/* 64-bit FNV-1a hash of a valid configuration: the bytes of these 32-bit
+ * little-endian fields in this order: r, n_ra, n_va, log2_g, cbn[0 .. n_ra+n_va),
+ * cl_bs[0 .. n_ra), seed_mangle, seed_bv, seed_va[0 .. n_va). Fields beyond the
+ * counts are not hashed. 0 if the configuration is invalid. */
+uint64_t cbaa_config_hash(const cbaa_config* h_cfg);
+
+/* Reads the cube's header back (synchronises `stream`): CBAA_OK if it is a
+ * valid header of this configuration, CBAA_ECONFIG if it is missing, of
+ * another configuration or marked CBAA_CUBE_MIXED. */
+int cbaa_cube_check(const cbaa_config* h_cfg, const void* d_cube, void* stream);
 
 /* Bytes of scratch the partitioned update path needs to take n_pairs packets
  * into n_cubes (1 or 2) cubes in one pass. Smaller (non-zero) scratch makes
@@ -143,8 +185,9 @@ uint64_t cbaa_restore_scratch_bytes(const cbaa_config* h_cfg, uint64_t capacity)
 
 /* ---- local server ---------------------------------------------------- */
 
-/* Starts a window: zeroes a cube of cbaa_cube_bytes bytes (Sec. 3.1: all
- * bits vectors start at zero). d_cube must be 16-byte aligned. */
+/* Starts a window: writes the header and zeroes the bits of a cube of
+ * cbaa_cube_bytes bytes (Sec. 3.1: all bits vectors start at zero). d_cube
+ * must be 16-byte aligned. */
 int cbaa_cube_init(const cbaa_config* h_cfg, void* d_cube, void* stream);
 
 /* Alg. 1 for a batch: for every pair k, with (host, peer) = (src, dst) for
@@ -188,7 +231,7 @@ typedef struct cbaa_stream_batch {
 
 /* Tile and partition shapes of the partitioned update (0 = library default):
  * chunk_pairs  pairs per histogram/scatter block (multiple of 1024, <= 2^22)
- * seg_records  records per apply work item (>= 1024)
+ * seg_records  records per apply work item (1024 .. 2^24)
  * apply_blocks persistent blocks of the apply step (1..65536) */
 typedef struct cbaa_tuning {
   uint32_t chunk_pairs;
@@ -219,7 +262,9 @@ int cbaa_update_batch(const cbaa_config* h_cfg, const cbaa_stream_batch* h_strea
 /* ---- global server --------------------------------------------------- */
 
 /* Sec. 3.3: d_dst = bitwise OR of k cubes of one configuration. h_srcs is a
- * host array of k >= 1 device pointers; d_dst may equal any of them. */
+ * host array of k >= 1 device pointers; d_dst (not NULL) may equal any of
+ * them. d_dst gets a valid header when every source has one of this
+ * configuration, else a header marked CBAA_CUBE_MIXED. */
 int cbaa_merge_or(const cbaa_config* h_cfg, void* d_dst, const void* const* h_srcs, int k,
                   void* stream);
 
@@ -237,10 +282,21 @@ int cbaa_column_zeros(const cbaa_config* h_cfg, const void* d_cube, uint16_t* d_
  * d_stats (device) receives the counters, n_hosts being the full count n
  * (when n > capacity the output holds an unspecified subset: call again
  * with more capacity). d_scratch holds cbaa_restore_scratch_bytes(capacity).
+ * max_checks bounds the tuple check's work: once it has examined more than
+ * max_checks tuples (partial tuples whose AND is counted, and complete
+ * CP-valid tuples), it stops, every wave exits soon after (each overshoots
+ * by at most a few hundred tuples) and d_stats->status gets
+ * CBAA_STATUS_BUDGET (the list then holds the hosts found so far, n_hosts
+ * counting them). 0 selects CBAA_DEFAULT_MAX_CHECKS. An
+ * over-full window (every column hot) thus ends in bounded time instead of
+ * enumerating up to 2^(32 - r) tuples per sketch.
+ * A cube without this configuration's valid header gives status
+ * CBAA_STATUS_CONFIG and no hosts.
  * Asynchronous: read d_stats after synchronising the stream. */
+#define CBAA_DEFAULT_MAX_CHECKS (1ull << 28)
 int cbaa_restore(const cbaa_config* h_cfg, const void* d_cube, double theta, int thr_rule,
-                 void* d_scratch, uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
-                 cbaa_restore_stats* d_stats, void* stream);
+                 uint64_t max_checks, void* d_scratch, uint64_t scratch_bytes, cbaa_host* d_out,
+                 uint64_t capacity, cbaa_restore_stats* d_stats, void* stream);
 
 /* The global server's window end in one call (Sec. 3.3): d_dst = bitwise OR
  * of the k router cubes (as cbaa_merge_or; d_dst may equal a source), then
@@ -248,21 +304,23 @@ int cbaa_restore(const cbaa_config* h_cfg, const void* d_cube, double theta, int
  * per-column zero counts the restore starts from are computed in one pass
  * over the sources, so the merged cube is written once and never re-read
  * for the counts; larger k merges first. Arguments and results as for
- * cbaa_merge_or and cbaa_restore.
+ * cbaa_merge_or and cbaa_restore; status CBAA_STATUS_CONFIG when any source
+ * lacks this configuration's valid header.
  * d_dst may be NULL when k <= 16: the merged cube is then not stored, and
  * the restore reads each column it needs (hot columns, VA columns) as the OR
  * of the sources. The restored list and stats are those of the stored case.
  * NULL with k > 16 returns CBAA_EINVAL. */
 int cbaa_merge_restore(const cbaa_config* h_cfg, void* d_dst, const void* const* h_srcs, int k,
-                       double theta, int thr_rule, void* d_scratch, uint64_t scratch_bytes,
-                       cbaa_host* d_out, uint64_t capacity, cbaa_restore_stats* d_stats,
-                       void* stream);
+                       double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
+                       uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
+                       cbaa_restore_stats* d_stats, void* stream);
 
 /* Thm. 2 estimate for given inner IPs: d_est[k] (double), d_zeros[k] (Z of
  * the union column) and, if d_layer_zeros is not NULL, the zero count of each
  * of the host's n_ra+n_va columns at d_layer_zeros[k*A + a] (uint16). eps is
  * measured from the cube as in cbaa_restore. d_scratch holds
- * cbaa_restore_scratch_bytes(cfg, 0). */
+ * cbaa_restore_scratch_bytes(cfg, 0). The header is not checked (see
+ * cbaa_cube_check). */
 int cbaa_estimate(const cbaa_config* h_cfg, const void* d_cube, const uint32_t* d_hosts,
                   uint64_t n, double* d_est, uint16_t* d_zeros, uint16_t* d_layer_zeros,
                   void* d_scratch, uint64_t scratch_bytes, void* stream);

@@ -27,7 +27,15 @@ CBAA_OK, CBAA_EINVAL, CBAA_ECONFIG, CBAA_ESCRATCH, CBAA_EHIP = 0, -1, -2, -3, -4
 SIDE_SRC, SIDE_DST = 0, 1
 THR_THM2, THR_PAPER = 0, 1
 FLAG_SATURATED = 1
+STATUS_CONFIG, STATUS_BUDGET = 1, 2
 MAX_RA, MAX_VA = 4, 2
+HEADER_BYTES = 256
+HEADER_WORDS = HEADER_BYTES // 8
+CUBE_MAGIC = 0x4542554341414243
+CUBE_VALID, CUBE_MIXED = 0, 1
+DEFAULT_MAX_CHECKS = 1 << 28
+STATS_FIELDS = ("n_hosts", "hot_columns", "partial_checked", "tuples_checked", "tuple_space",
+                "status")
 
 
 class CbaaError(RuntimeError):
@@ -44,8 +52,10 @@ class cbaa_config(C.Structure):
 
 
 class cbaa_restore_stats(C.Structure):
-    _fields_ = [("n_hosts", C.c_uint64), ("hot_columns", C.c_uint64),
-                ("partial_checked", C.c_uint64), ("tuples_checked", C.c_uint64)]
+    _fields_ = [(f, C.c_uint64) for f in STATS_FIELDS]
+
+
+STATS_BYTES = C.sizeof(cbaa_restore_stats)
 
 
 class cbaa_stream_batch(C.Structure):
@@ -133,6 +143,8 @@ def lib():
         "cbaa_config_default": (i32, [cfgp]),
         "cbaa_config_validate": (i32, [cfgp]),
         "cbaa_cube_bytes": (u64, [cfgp]),
+        "cbaa_config_hash": (u64, [cfgp]),
+        "cbaa_cube_check": (i32, [cfgp, vp, vp]),
         "cbaa_update_scratch_bytes": (u64, [cfgp, u64, i32]),
         "cbaa_restore_scratch_bytes": (u64, [cfgp, u64]),
         "cbaa_cube_init": (i32, [cfgp, vp, vp]),
@@ -144,10 +156,10 @@ def lib():
         "cbaa_update_batch": (i32, [cfgp, C.POINTER(cbaa_stream_batch), i32,
                                     C.POINTER(cbaa_tuning), vp, u64, vp]),
         "cbaa_column_zeros": (i32, [cfgp, vp, vp, vp, vp]),
-        "cbaa_restore": (i32, [cfgp, vp, dbl, i32, vp, u64, vp, u64, vp, vp]),
+        "cbaa_restore": (i32, [cfgp, vp, dbl, i32, u64, vp, u64, vp, u64, vp, vp]),
         "cbaa_estimate": (i32, [cfgp, vp, vp, u64, vp, vp, vp, vp, u64, vp]),
-        "cbaa_merge_restore": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, vp, u64, vp, u64, vp,
-                                     vp]),
+        "cbaa_merge_restore": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, u64, vp, u64, vp, u64,
+                                     vp, vp]),
         "cbaa_mlp_param_count": (C.c_uint32, [C.c_uint32]),
         "cbaa_mlp_init": (i32, [C.c_uint32, C.c_uint32, i32, vp, vp, vp]),
         "cbaa_mlp_features": (i32, [cfgp, vp, vp, u64, C.c_uint32, vp, vp, u64, vp]),
@@ -188,14 +200,22 @@ def _stream(stream) -> Optional[int]:
     return int(stream)
 
 
-def _dev_ptr(t: Optional[torch.Tensor], name: str) -> Optional[int]:
+def _dev_ptr(t: Optional[torch.Tensor], name: str, min_bytes: int = 0) -> Optional[int]:
+    """Device address of a contiguous tensor holding at least min_bytes."""
     if t is None:
         return None
     if not t.is_cuda:
         raise ValueError(f"{name} must be a device tensor")
     if not t.is_contiguous():
         raise ValueError(f"{name} must be contiguous")
+    nbytes = t.numel() * t.element_size()
+    if nbytes < min_bytes:
+        raise ValueError(f"{name} holds {nbytes} bytes, the call needs {min_bytes}")
     return t.data_ptr()
+
+
+def _cube_ptr(cfg, t: Optional[torch.Tensor], name: str) -> Optional[int]:
+    return _dev_ptr(t, name, cbaa_cube_bytes(cfg))
 
 
 # ---- C ABI, one to one ------------------------------------------------------
@@ -224,6 +244,20 @@ def cbaa_cube_bytes(cfg) -> int:
     return int(lib().cbaa_cube_bytes(C.byref(_cfg(cfg))))
 
 
+def cbaa_config_hash(cfg) -> int:
+    return int(lib().cbaa_config_hash(C.byref(_cfg(cfg))))
+
+
+def cbaa_cube_check(cfg, cube: torch.Tensor, stream=None) -> int:
+    """CBAA_OK, or CBAA_ECONFIG when the cube lacks this configuration's valid
+    header (returned, not raised; synchronises the stream)."""
+    rc = int(lib().cbaa_cube_check(C.byref(_cfg(cfg)), _cube_ptr(cfg, cube, "cube"),
+                                   _stream(stream)))
+    if rc not in (CBAA_OK, CBAA_ECONFIG):
+        _check(rc, "cbaa_cube_check")
+    return rc
+
+
 def cbaa_update_scratch_bytes(cfg, n_pairs: int, n_cubes: int) -> int:
     return int(lib().cbaa_update_scratch_bytes(C.byref(_cfg(cfg)), n_pairs, n_cubes))
 
@@ -233,7 +267,7 @@ def cbaa_restore_scratch_bytes(cfg, capacity: int) -> int:
 
 
 def cbaa_cube_init(cfg, cube: torch.Tensor, stream=None) -> None:
-    _check(lib().cbaa_cube_init(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"), _stream(stream)),
+    _check(lib().cbaa_cube_init(C.byref(_cfg(cfg)), _cube_ptr(cfg, cube, "cube"), _stream(stream)),
            "cbaa_cube_init")
 
 
@@ -248,7 +282,7 @@ def cbaa_update(cfg, cube: torch.Tensor, pairs: torch.Tensor, side: int,
                 scratch: Optional[torch.Tensor] = None, stream=None) -> None:
     p, n = _pairs_ptr(pairs)
     sb = scratch.numel() * scratch.element_size() if scratch is not None else 0
-    _check(lib().cbaa_update(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"), p, n, side,
+    _check(lib().cbaa_update(C.byref(_cfg(cfg)), _cube_ptr(cfg, cube, "cube"), p, n, side,
                              _dev_ptr(scratch, "scratch"), sb, _stream(stream)), "cbaa_update")
 
 
@@ -256,15 +290,15 @@ def cbaa_update2(cfg, cube_src: torch.Tensor, cube_dst: torch.Tensor, pairs: tor
                  scratch: Optional[torch.Tensor] = None, stream=None) -> None:
     p, n = _pairs_ptr(pairs)
     sb = scratch.numel() * scratch.element_size() if scratch is not None else 0
-    _check(lib().cbaa_update2(C.byref(_cfg(cfg)), _dev_ptr(cube_src, "cube_src"),
-                              _dev_ptr(cube_dst, "cube_dst"), p, n, _dev_ptr(scratch, "scratch"),
+    _check(lib().cbaa_update2(C.byref(_cfg(cfg)), _cube_ptr(cfg, cube_src, "cube_src"),
+                              _cube_ptr(cfg, cube_dst, "cube_dst"), p, n, _dev_ptr(scratch, "scratch"),
                               sb, _stream(stream)), "cbaa_update2")
 
 
 BATCH_FRESH = 1
 
 
-def _stream_table(streams):
+def _stream_table(cfg, streams):
     """streams: sequence of (pairs, cube, cube_dst or None, side[, flags])."""
     arr = (cbaa_stream_batch * len(streams))()
     for i, entry in enumerate(streams):
@@ -273,8 +307,8 @@ def _stream_table(streams):
         p, n = _pairs_ptr(pairs)
         arr[i].d_pairs = p
         arr[i].n_pairs = n
-        arr[i].d_cube = _dev_ptr(cube, "cube")
-        arr[i].d_cube_dst = _dev_ptr(cube_dst, "cube_dst")
+        arr[i].d_cube = _cube_ptr(cfg, cube, "cube")
+        arr[i].d_cube_dst = _cube_ptr(cfg, cube_dst, "cube_dst")
         arr[i].side = side
     return arr
 
@@ -290,53 +324,61 @@ def _tuning(t) -> Optional[cbaa_tuning]:
 
 def cbaa_update_batch_scratch_bytes(cfg, streams, tuning=None) -> int:
     t = _tuning(tuning)
-    return int(lib().cbaa_update_batch_scratch_bytes(C.byref(_cfg(cfg)), _stream_table(streams),
+    return int(lib().cbaa_update_batch_scratch_bytes(C.byref(_cfg(cfg)), _stream_table(cfg, streams),
                                                      len(streams), C.byref(t) if t else None))
 
 
 def cbaa_update_batch(cfg, streams, scratch: torch.Tensor, tuning=None, stream=None) -> None:
     t = _tuning(tuning)
     sb = scratch.numel() * scratch.element_size()
-    _check(lib().cbaa_update_batch(C.byref(_cfg(cfg)), _stream_table(streams), len(streams),
+    _check(lib().cbaa_update_batch(C.byref(_cfg(cfg)), _stream_table(cfg, streams), len(streams),
                                    C.byref(t) if t else None, _dev_ptr(scratch, "scratch"), sb,
                                    _stream(stream)), "cbaa_update_batch")
 
 
 def cbaa_merge_or(cfg, dst: torch.Tensor, srcs: Sequence[torch.Tensor], stream=None) -> None:
-    arr = (C.c_void_p * len(srcs))(*[_dev_ptr(s, "src") for s in srcs])
-    _check(lib().cbaa_merge_or(C.byref(_cfg(cfg)), _dev_ptr(dst, "dst"), arr, len(srcs),
+    if dst is None:
+        raise ValueError("cbaa_merge_or needs a destination cube")
+    arr = (C.c_void_p * len(srcs))(*[_cube_ptr(cfg, s, "src") for s in srcs])
+    _check(lib().cbaa_merge_or(C.byref(_cfg(cfg)), _cube_ptr(cfg, dst, "dst"), arr, len(srcs),
                                _stream(stream)), "cbaa_merge_or")
 
 
 def cbaa_column_zeros(cfg, cube: torch.Tensor, zeros: torch.Tensor, ones: torch.Tensor,
                       stream=None) -> None:
-    _check(lib().cbaa_column_zeros(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"),
-                                   _dev_ptr(zeros, "zeros"), _dev_ptr(ones, "ones"),
+    c = Config.from_dict(cfg) if isinstance(cfg, dict) else cfg
+    _check(lib().cbaa_column_zeros(C.byref(_cfg(cfg)), _cube_ptr(cfg, cube, "cube"),
+                                   _dev_ptr(zeros, "zeros", 2 * c.n_sketches * c.slab_words),
+                                   _dev_ptr(ones, "ones", 4 * c.n_sketches * c.n_arrays),
                                    _stream(stream)), "cbaa_column_zeros")
 
 
 def cbaa_restore(cfg, cube: torch.Tensor, theta: float, rule: int, scratch: torch.Tensor,
                  out: Optional[torch.Tensor], capacity: int, stats: torch.Tensor,
-                 stream=None) -> None:
+                 stream=None, max_checks: int = 0) -> None:
     sb = scratch.numel() * scratch.element_size()
-    _check(lib().cbaa_restore(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"), float(theta), rule,
-                              _dev_ptr(scratch, "scratch"), sb,
-                              _dev_ptr(out, "out") if capacity else None, capacity,
-                              _dev_ptr(stats, "stats"), _stream(stream)), "cbaa_restore")
+    _check(lib().cbaa_restore(C.byref(_cfg(cfg)), _cube_ptr(cfg, cube, "cube"), float(theta), rule,
+                              max_checks, _dev_ptr(scratch, "scratch"), sb,
+                              _dev_ptr(out, "out", capacity * HOST_BYTES) if capacity else None,
+                              capacity, _dev_ptr(stats, "stats", STATS_BYTES), _stream(stream)),
+           "cbaa_restore")
 
 
 def cbaa_merge_restore(cfg, dst: Optional[torch.Tensor], srcs: Sequence[torch.Tensor],
                        theta: float, rule: int, scratch: torch.Tensor, out: Optional[torch.Tensor],
-                       capacity: int, stats: torch.Tensor, stream=None) -> None:
+                       capacity: int, stats: torch.Tensor, stream=None,
+                       max_checks: int = 0) -> None:
     """dst None: the merged cube is not stored (at most 16 sources)."""
-    arr = (C.c_void_p * len(srcs))(*[_dev_ptr(x, "src") for x in srcs])
+    arr = (C.c_void_p * len(srcs))(*[_cube_ptr(cfg, x, "src") for x in srcs])
     sb = scratch.numel() * scratch.element_size()
     _check(lib().cbaa_merge_restore(C.byref(_cfg(cfg)),
-                                    _dev_ptr(dst, "dst") if dst is not None else None,
+                                    _cube_ptr(cfg, dst, "dst") if dst is not None else None,
                                     arr, len(srcs),
-                                    float(theta), rule, _dev_ptr(scratch, "scratch"), sb,
-                                    _dev_ptr(out, "out") if capacity else None, capacity,
-                                    _dev_ptr(stats, "stats"), _stream(stream)),
+                                    float(theta), rule, max_checks, _dev_ptr(scratch, "scratch"),
+                                    sb,
+                                    _dev_ptr(out, "out", capacity * HOST_BYTES) if capacity
+                                    else None, capacity,
+                                    _dev_ptr(stats, "stats", STATS_BYTES), _stream(stream)),
            "cbaa_merge_restore")
 
 
@@ -345,11 +387,12 @@ def cbaa_estimate(cfg, cube: torch.Tensor, hosts: torch.Tensor, est: torch.Tenso
                   scratch: torch.Tensor, stream=None) -> None:
     n = int(hosts.numel())
     sb = scratch.numel() * scratch.element_size()
-    _check(lib().cbaa_estimate(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"),
-                               _dev_ptr(hosts, "hosts") if n else None, n,
-                               _dev_ptr(est, "est") if n else None,
-                               _dev_ptr(zeros, "zeros") if n else None,
-                               _dev_ptr(layer_zeros, "layer_zeros") if n else None,
+    A = (Config.from_dict(cfg) if isinstance(cfg, dict) else cfg).n_arrays
+    _check(lib().cbaa_estimate(C.byref(_cfg(cfg)), _cube_ptr(cfg, cube, "cube"),
+                               _dev_ptr(hosts, "hosts", 4 * n) if n else None, n,
+                               _dev_ptr(est, "est", 8 * n) if n else None,
+                               _dev_ptr(zeros, "zeros", 2 * n) if n else None,
+                               _dev_ptr(layer_zeros, "layer_zeros", 2 * n * A) if n else None,
                                _dev_ptr(scratch, "scratch"), sb, _stream(stream)),
            "cbaa_estimate")
 
@@ -370,9 +413,10 @@ def cbaa_mlp_features(cfg, cube: torch.Tensor, hosts: torch.Tensor, n_features: 
                       x: torch.Tensor, scratch: torch.Tensor, stream=None) -> None:
     n = int(hosts.numel())
     sb = scratch.numel() * scratch.element_size()
-    _check(lib().cbaa_mlp_features(C.byref(_cfg(cfg)), _dev_ptr(cube, "cube"),
-                                   _dev_ptr(hosts, "hosts") if n else None, n, n_features,
-                                   _dev_ptr(x, "x") if n else None, _dev_ptr(scratch, "scratch"),
+    _check(lib().cbaa_mlp_features(C.byref(_cfg(cfg)), _cube_ptr(cfg, cube, "cube"),
+                                   _dev_ptr(hosts, "hosts", 4 * n) if n else None, n, n_features,
+                                   _dev_ptr(x, "x", 4 * n * n_features) if n else None,
+                                   _dev_ptr(scratch, "scratch"),
                                    sb, _stream(stream)), "cbaa_mlp_features")
 
 
@@ -419,7 +463,12 @@ def scratch_tensor(nbytes: int, device="cuda") -> torch.Tensor:
 
 
 def stats_tensor(device="cuda") -> torch.Tensor:
-    return torch.zeros(4, dtype=torch.int64, device=device)
+    return torch.zeros(len(STATS_FIELDS), dtype=torch.int64, device=device)
+
+
+def stats_dict(st: torch.Tensor) -> dict:
+    """A cbaa_restore_stats tensor (read back to the host) as a dict."""
+    return dict(zip(STATS_FIELDS, (int(v) for v in st.cpu().tolist())))
 
 
 def host_list(out: torch.Tensor, n: int) -> np.ndarray:
@@ -428,7 +477,7 @@ def host_list(out: torch.Tensor, n: int) -> np.ndarray:
 
 
 def restore(cfg, cube: torch.Tensor, theta: float, rule: int = THR_THM2, capacity: int = 1 << 16,
-            stream=None) -> tuple[np.ndarray, dict]:
+            stream=None, max_checks: int = 0) -> tuple[np.ndarray, dict]:
     """Restores the super hosts of `cube`; grows the output until it fits.
     Returns (structured array sorted by ip, stats dict)."""
     dev = cube.device
@@ -436,13 +485,14 @@ def restore(cfg, cube: torch.Tensor, theta: float, rule: int = THR_THM2, capacit
         scratch = scratch_tensor(cbaa_restore_scratch_bytes(cfg, capacity), dev)
         out = torch.empty(max(capacity, 1) * HOST_BYTES, dtype=torch.uint8, device=dev)
         st = stats_tensor(dev)
-        cbaa_restore(cfg, cube, theta, rule, scratch, out, capacity, st, stream)
+        cbaa_restore(cfg, cube, theta, rule, scratch, out, capacity, st, stream,
+                     max_checks=max_checks)
         torch.cuda.synchronize(dev)
-        s = [int(v) for v in st.cpu().tolist()]
-        stats = dict(n_hosts=s[0], hot_columns=s[1], partial_checked=s[2], tuples_checked=s[3])
-        if s[0] <= capacity:
-            return host_list(out, s[0]), stats
-        capacity = s[0]
+        stats = stats_dict(st)
+        n = stats["n_hosts"]
+        if n <= capacity:
+            return host_list(out, n), stats
+        capacity = n
 
 
 def estimate(cfg, cube: torch.Tensor, hosts: np.ndarray, layers: bool = False, stream=None):
@@ -470,4 +520,21 @@ def pairs_to_device(pairs: np.ndarray, device="cuda") -> torch.Tensor:
 
 
 def cube_to_numpy(cube: torch.Tensor) -> np.ndarray:
-    return cube.cpu().numpy().view(np.uint64)
+    """The cube's bits (the words after its header) as uint64."""
+    return cube.cpu().numpy().view(np.uint64)[HEADER_WORDS:]
+
+
+def cube_header(cube: torch.Tensor) -> np.ndarray:
+    """The cube's header: 32 uint64 words."""
+    return cube[:HEADER_WORDS].cpu().numpy().view(np.uint64)
+
+
+def cube_from_bits(cfg, bits: np.ndarray, device="cuda") -> torch.Tensor:
+    """A device cube with a valid header of `cfg` holding the given bits."""
+    cube = new_cube(cfg, device)
+    b = np.ascontiguousarray(bits, dtype=np.uint64)
+    if b.size != cube.numel() - HEADER_WORDS:
+        raise ValueError(f"{b.size} words of bits, the configuration's cube holds "
+                         f"{cube.numel() - HEADER_WORDS}")
+    cube[HEADER_WORDS:].copy_(torch.from_numpy(b.view(np.int64)))
+    return cube

@@ -81,6 +81,24 @@ bool make_dims(const cbaa_config* c, Dims* o) {
   d.seed_bv = c->seed_bv;
   for (uint32_t j = 0; j < CBAA_MAX_VA; ++j) d.seed_va[j] = c->seed_va[j];
   d.words = (uint64_t)d.S * d.R * d.W;
+  // FNV-1a over the defined fields' little-endian bytes (cbaa_config_hash)
+  uint64_t h = 0xCBF29CE484222325ull;
+  auto mix = [&](uint32_t v) {
+    for (int k = 0; k < 4; ++k) {
+      h ^= (v >> (8 * k)) & 0xFFu;
+      h *= 0x100000001B3ull;
+    }
+  };
+  mix(c->r);
+  mix(c->n_ra);
+  mix(c->n_va);
+  mix(c->log2_g);
+  for (uint32_t a = 0; a < d.A; ++a) mix(c->cbn[a]);
+  for (uint32_t i = 0; i < d.n_ra; ++i) mix(c->cl_bs[i]);
+  mix(c->seed_mangle);
+  mix(c->seed_bv);
+  for (uint32_t j = 0; j < d.n_va; ++j) mix(c->seed_va[j]);
+  d.hash = h;
   *o = d;
   return true;
 }
@@ -92,6 +110,14 @@ using namespace cbaa;
 #define CHECK_DIMS(cfg, d)                 \
   Dims d;                                  \
   if (!make_dims((cfg), &d)) return CBAA_ECONFIG
+
+// The bits of a caller's cube (after its header).
+static inline uint64_t* bits_of(void* cube) {
+  return cube ? (uint64_t*)((char*)cube + CBAA_HEADER_BYTES) : nullptr;
+}
+static inline const uint64_t* bits_of(const void* cube) {
+  return cube ? (const uint64_t*)((const char*)cube + CBAA_HEADER_BYTES) : nullptr;
+}
 
 #define REQUIRE(cond, ...)        \
   do {                            \
@@ -132,7 +158,30 @@ int cbaa_config_validate(const cbaa_config* cfg) {
 uint64_t cbaa_cube_bytes(const cbaa_config* cfg) {
   Dims d;
   if (!make_dims(cfg, &d)) return 0;
-  return d.words * 8u;
+  return CBAA_HEADER_BYTES + d.words * 8u;
+}
+
+uint64_t cbaa_config_hash(const cbaa_config* cfg) {
+  Dims d;
+  if (!make_dims(cfg, &d)) return 0;
+  return d.hash;
+}
+
+int cbaa_cube_check(const cbaa_config* cfg, const void* d_cube, void* stream) {
+  CHECK_DIMS(cfg, d);
+  REQUIRE(d_cube && ((uintptr_t)d_cube & 15u) == 0, "cube must be a non-null 16-byte aligned pointer");
+  uint64_t h[4];
+  hipStream_t s = (hipStream_t)stream;
+  hipError_t e = hipMemcpyAsync(h, d_cube, sizeof h, hipMemcpyDeviceToHost, s);
+  if (e == hipSuccess) e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return hip_fail(e, "header read");
+  if (h[0] != CBAA_CUBE_MAGIC) return set_error("no cube header (magic missing)"), CBAA_ECONFIG;
+  if (h[1] != d.hash) return set_error("cube built with another configuration"), CBAA_ECONFIG;
+  if (h[2] != d.words * 8u) return set_error("cube size differs from the configuration's"), CBAA_ECONFIG;
+  if ((uint32_t)h[3] != CBAA_ABI_VERSION) return set_error("cube header of ABI version %u", (uint32_t)h[3]), CBAA_ECONFIG;
+  if ((h[3] >> 32) != CBAA_CUBE_VALID)
+    return set_error("cube holds bits of another configuration or of a cube without a header"), CBAA_ECONFIG;
+  return CBAA_OK;
 }
 
 uint64_t cbaa_update_scratch_bytes(const cbaa_config* cfg, uint64_t n_pairs, int n_cubes) {
@@ -150,7 +199,7 @@ uint64_t cbaa_restore_scratch_bytes(const cbaa_config* cfg, uint64_t capacity) {
 int cbaa_cube_init(const cbaa_config* cfg, void* d_cube, void* stream) {
   CHECK_DIMS(cfg, d);
   REQUIRE(d_cube && ((uintptr_t)d_cube & 15u) == 0, "cube must be a non-null 16-byte aligned pointer");
-  return launch_fill_zero((uint64_t*)d_cube, d.words, (hipStream_t)stream);
+  return launch_cube_init(d, bits_of(d_cube), (hipStream_t)stream);
 }
 
 static int update_common(const Dims& d, void* c0, void* c1, const uint32_t* pairs, uint64_t n,
@@ -163,7 +212,7 @@ static int update_common(const Dims& d, void* c0, void* c1, const uint32_t* pair
   REQUIRE(n < (1ull << 40), "n_pairs too large");
   hipStream_t s = (hipStream_t)stream;
   if (scratch == nullptr || scratch_bytes == 0 || !partitioned_supported(d))
-    return launch_update_direct(d, (uint64_t*)c0, (uint64_t*)c1, pairs, n, side, s);
+    return launch_update_direct(d, bits_of(c0), bits_of(c1), pairs, n, side, s);
   if (scratch_bytes < partitioned_min_scratch_bytes(d, c1 ? 2 : 1, n)) {
     set_error("update scratch of %llu bytes is below the minimum %llu",
               (unsigned long long)scratch_bytes,
@@ -171,7 +220,7 @@ static int update_common(const Dims& d, void* c0, void* c1, const uint32_t* pair
     return CBAA_ESCRATCH;
   }
   REQUIRE(((uintptr_t)scratch & 255u) == 0, "scratch must be 256-byte aligned");
-  return launch_update_partitioned(d, (uint64_t*)c0, (uint64_t*)c1, pairs, n, side, scratch,
+  return launch_update_partitioned(d, bits_of(c0), bits_of(c1), pairs, n, side, scratch,
                                    scratch_bytes, s);
 }
 
@@ -222,8 +271,8 @@ static int check_streams(const Dims& d, const cbaa_stream_batch* h, int k, Strea
     out[i].fresh = (s.flags & CBAA_BATCH_FRESH) ? 1 : 0;
     out[i].pairs = s.d_pairs;
     out[i].n = s.n_pairs;
-    out[i].cube0 = (uint64_t*)s.d_cube;
-    out[i].cube1 = (uint64_t*)s.d_cube_dst;
+    out[i].cube0 = bits_of(s.d_cube);
+    out[i].cube1 = bits_of(s.d_cube_dst);
     out[i].side = nc == 2 ? CBAA_SIDE_SRC : s.side;
   }
   return nc;
@@ -260,14 +309,16 @@ int cbaa_update_batch(const cbaa_config* cfg, const cbaa_stream_batch* h, int k,
 int cbaa_merge_or(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
                   void* stream) {
   CHECK_DIMS(cfg, d);
-  // a null destination (merge not stored) is served by the one-pass scan,
-  // which takes up to 16 sources
-  REQUIRE(((uintptr_t)d_dst & 15u) == 0, "destination must be 16-byte aligned");
+  REQUIRE(d_dst && ((uintptr_t)d_dst & 15u) == 0, "destination must be a non-null 16-byte aligned pointer");
   REQUIRE(h_srcs && k >= 1, "need at least one source cube");
-  REQUIRE(d_dst || k <= 16, "more than 16 source cubes need a destination cube");
   for (int i = 0; i < k; ++i)
     REQUIRE(h_srcs[i] && ((uintptr_t)h_srcs[i] & 15u) == 0, "source %d null or not 16-byte aligned", i);
-  return launch_merge_or(d, (uint64_t*)d_dst, (const uint64_t* const*)h_srcs, k, (hipStream_t)stream);
+  const uint64_t* stack[64];
+  const uint64_t** b = k <= 64 ? stack : new const uint64_t*[k];
+  for (int i = 0; i < k; ++i) b[i] = bits_of(h_srcs[i]);
+  const int rc = launch_merge_or(d, bits_of(d_dst), b, k, (hipStream_t)stream);
+  if (b != stack) delete[] b;
+  return rc;
 }
 
 int cbaa_column_zeros(const cbaa_config* cfg, const void* d_cube, uint16_t* d_zeros,
@@ -277,12 +328,12 @@ int cbaa_column_zeros(const cbaa_config* cfg, const void* d_cube, uint16_t* d_ze
   REQUIRE(d_zeros && d_ones, "null output");
   REQUIRE(((uintptr_t)d_zeros & 3u) == 0 && ((uintptr_t)d_ones & 3u) == 0,
           "outputs must be 4-byte aligned");
-  return launch_column_zeros(d, (const uint64_t*)d_cube, d_zeros, d_ones, (hipStream_t)stream);
+  return launch_column_zeros(d, bits_of(d_cube), d_zeros, d_ones, (hipStream_t)stream);
 }
 
 int cbaa_restore(const cbaa_config* cfg, const void* d_cube, double theta, int thr_rule,
-                 void* d_scratch, uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
-                 cbaa_restore_stats* d_stats, void* stream) {
+                 uint64_t max_checks, void* d_scratch, uint64_t scratch_bytes, cbaa_host* d_out,
+                 uint64_t capacity, cbaa_restore_stats* d_stats, void* stream) {
   CHECK_DIMS(cfg, d);
   REQUIRE(d_cube && ((uintptr_t)d_cube & 15u) == 0, "cube must be 16-byte aligned");
   REQUIRE(thr_rule == CBAA_THR_THM2 || thr_rule == CBAA_THR_PAPER, "unknown threshold rule");
@@ -300,14 +351,15 @@ int cbaa_restore(const cbaa_config* cfg, const void* d_cube, double theta, int t
   // exp(-theta/g) is taken once here so that the threshold of every sketch
   // is computed from the same IEEE double on the device.
   const double x = exp(-theta / (double)d.g);
-  return launch_restore(d, (const uint64_t*)d_cube, x, thr_rule, d_scratch, capacity, d_out,
-                        d_stats, (hipStream_t)stream);
+  return launch_restore(d, bits_of(d_cube), x, thr_rule,
+                        max_checks ? max_checks : CBAA_DEFAULT_MAX_CHECKS, d_scratch, capacity,
+                        d_out, d_stats, (hipStream_t)stream);
 }
 
 int cbaa_merge_restore(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
-                       double theta, int thr_rule, void* d_scratch, uint64_t scratch_bytes,
-                       cbaa_host* d_out, uint64_t capacity, cbaa_restore_stats* d_stats,
-                       void* stream) {
+                       double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
+                       uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
+                       cbaa_restore_stats* d_stats, void* stream) {
   CHECK_DIMS(cfg, d);
   // a null destination (merge not stored) is served by the one-pass scan,
   // which takes up to 16 sources
@@ -329,8 +381,14 @@ int cbaa_merge_restore(const cbaa_config* cfg, void* d_dst, const void* const* h
     return CBAA_ESCRATCH;
   }
   const double x = exp(-theta / (double)d.g);
-  return launch_merge_restore(d, (uint64_t*)d_dst, (const uint64_t* const*)h_srcs, k, x, thr_rule,
-                              d_scratch, capacity, d_out, d_stats, (hipStream_t)stream);
+  const uint64_t* stack[64];
+  const uint64_t** b = k <= 64 ? stack : new const uint64_t*[k];
+  for (int i = 0; i < k; ++i) b[i] = bits_of(h_srcs[i]);
+  const int rc = launch_merge_restore(d, bits_of(d_dst), b, k, x, thr_rule,
+                                      max_checks ? max_checks : CBAA_DEFAULT_MAX_CHECKS,
+                                      d_scratch, capacity, d_out, d_stats, (hipStream_t)stream);
+  if (b != stack) delete[] b;
+  return rc;
 }
 
 int cbaa_estimate(const cbaa_config* cfg, const void* d_cube, const uint32_t* d_hosts, uint64_t n,
@@ -346,7 +404,7 @@ int cbaa_estimate(const cbaa_config* cfg, const void* d_cube, const uint32_t* d_
   if (n == 0) return CBAA_OK;
   REQUIRE(d_hosts && d_est && d_zeros, "null host list or output");
   REQUIRE(n < (1ull << 32), "n must be below 2^32");
-  return launch_estimate(d, (const uint64_t*)d_cube, d_hosts, n, d_est, d_zeros, d_layer_zeros,
+  return launch_estimate(d, bits_of(d_cube), d_hosts, n, d_est, d_zeros, d_layer_zeros,
                          d_scratch, (hipStream_t)stream);
 }
 
@@ -366,7 +424,7 @@ int cbaa_mlp_features(const cbaa_config* cfg, const void* d_cube, const uint32_t
   if (n == 0) return CBAA_OK;
   REQUIRE(d_hosts && d_x, "null host list or output");
   REQUIRE(n < (1ull << 32), "n must be below 2^32");
-  return launch_features(d, (const uint64_t*)d_cube, d_hosts, n, n_features, d_x, d_scratch,
+  return launch_features(d, bits_of(d_cube), d_hosts, n, n_features, d_x, d_scratch,
                          (hipStream_t)stream);
 }
 

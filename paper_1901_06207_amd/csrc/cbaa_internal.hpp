@@ -28,8 +28,38 @@ struct Dims {
   uint32_t cp[CBAA_MAX_RA];   // |CP(i)|
   uint32_t seed_mangle, seed_bv;
   uint32_t seed_va[CBAA_MAX_VA];
-  uint64_t words;             // 64-bit words per cube
+  uint64_t words;             // 64-bit words of bits per cube (after the header)
+  uint64_t hash;              // cbaa_config_hash of the configuration
 };
+
+// ---- cube header ---------------------------------------------------------
+// Kernels receive the cube's bits; its header sits the 256 bytes before them.
+
+constexpr uint64_t kHeaderWords = CBAA_HEADER_BYTES / 8;
+
+__host__ __device__ inline uint64_t* header_of(uint64_t* bits) { return bits - kHeaderWords; }
+__host__ __device__ inline const uint64_t* header_of(const uint64_t* bits) {
+  return bits - kHeaderWords;
+}
+
+__device__ inline bool header_ok(const uint64_t* h, const Dims& d) {
+  return h[0] == CBAA_CUBE_MAGIC && h[1] == d.hash && h[2] == d.words * 8u &&
+         h[3] == (uint64_t)CBAA_ABI_VERSION;   // state VALID in the high half
+}
+
+// Writes the four defined header words (state VALID or MIXED).
+__device__ inline void header_set(uint64_t* h, const Dims& d, uint32_t state) {
+  h[0] = CBAA_CUBE_MAGIC;
+  h[1] = d.hash;
+  h[2] = d.words * 8u;
+  h[3] = ((uint64_t)state << 32) | CBAA_ABI_VERSION;
+}
+
+// A cube about to receive more bits keeps a valid header only if it has one.
+__device__ inline void header_touch(uint64_t* bits, const Dims& d) {
+  uint64_t* h = header_of(bits);
+  if (!header_ok(h, d)) header_set(h, d, CBAA_CUBE_MIXED);
+}
 
 // ---- mixers (published definitions, written out here) -----------------
 
@@ -119,6 +149,8 @@ int hip_fail(hipError_t e, const char* what);
 
 // Launchers implemented in the kernel files. Each returns CBAA_OK or CBAA_EHIP.
 int launch_fill_zero(uint64_t* d, uint64_t words, hipStream_t s);
+// Zeroes a cube's bits and writes its whole header (valid).
+int launch_cube_init(const Dims& d, uint64_t* bits, hipStream_t s);
 int launch_update_direct(const Dims& d, uint64_t* cube0, uint64_t* cube1, const uint32_t* pairs,
                          uint64_t n, int side, hipStream_t s);
 int launch_update_partitioned(const Dims& d, uint64_t* cube0, uint64_t* cube1,
@@ -137,11 +169,13 @@ int launch_merge_or(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, i
 int launch_column_zeros(const Dims& d, const uint64_t* cube, uint16_t* zeros, uint32_t* ones,
                         hipStream_t s);
 uint64_t restore_scratch_bytes(const Dims& d, uint64_t capacity);
-int launch_restore(const Dims& d, const uint64_t* cube, double x_theta, int rule, void* scratch,
-                   uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s);
+int launch_restore(const Dims& d, const uint64_t* cube, double x_theta, int rule,
+                   uint64_t max_checks, void* scratch, uint64_t capacity, cbaa_host* out,
+                   cbaa_restore_stats* stats, hipStream_t s);
 int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
-                         double x_theta, int rule, void* scratch, uint64_t capacity,
-                         cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s);
+                         double x_theta, int rule, uint64_t max_checks, void* scratch,
+                         uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats,
+                         hipStream_t s);
 int launch_features(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
                     uint32_t F, float* x, void* scratch, hipStream_t s);
 int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,

@@ -165,8 +165,20 @@ __device__ inline uint32_t bin_of_record(const Dims& d, uint2 rec) {
   return (k * d.S + (rec.x & low_mask(d.r))) * d.R + (b >> 6);
 }
 
-__global__ void k_zero_words(uint32_t* p, uint32_t n) {
+// Zeroes the bin totals and counters, and sets the streams' cube headers: a
+// fresh stream's cubes get a valid header (they are rebuilt from empty), any
+// other cube keeps a valid header only if it has one. Two threads touching a
+// cube named by two streams write the same words.
+__global__ void k_begin(Dims d, Batch b, uint32_t* p, uint32_t n) {
   for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < n; i += gridDim.x * blockDim.x) p[i] = 0;
+  if (blockIdx.x == 0 && threadIdx.x < 2 * b.k) {
+    const StreamDesc& st = b.s[threadIdx.x / 2];
+    uint64_t* cube = (threadIdx.x & 1) ? st.cube1 : st.cube0;
+    if (cube) {
+      if (st.fresh) header_set(header_of(cube), d, CBAA_CUBE_VALID);
+      else header_touch(cube, d);
+    }
+  }
 }
 
 template <bool TWO>
@@ -514,6 +526,9 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
   int rc;
   bool any_fresh = false;
   for (uint32_t i = 0; i < b.k; ++i) any_fresh = any_fresh || b.s[i].fresh;
+  const uint32_t nt = b.k * b.nbins + 2;   // bin totals, the apply's and the scatter's counters
+  hipLaunchKernelGGL(k_begin, dim3((nt + 255) / 256), dim3(256), 0, s, d, b, L.tot, nt);
+  if ((rc = check("begin launch")) != CBAA_OK) return rc;
   if (b.total_chunks == 0) {   // no pairs at all: fresh cubes are just emptied
     for (uint32_t i = 0; i < b.k && any_fresh; ++i) {
       if (!b.s[i].fresh) continue;
@@ -522,9 +537,6 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
     }
     return CBAA_OK;
   }
-  const uint32_t nt = b.k * b.nbins + 2;   // bin totals, the apply's and the scatter's counters
-  hipLaunchKernelGGL(k_zero_words, dim3((nt + 255) / 256), dim3(256), 0, s, L.tot, nt);
-  if ((rc = check("zero launch")) != CBAA_OK) return rc;
   hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.tot);
   if ((rc = check("histogram launch")) != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_bases, dim3(b.k), dim3(kBlock), 0, s, b, L.tot, L.base, L.segpre, L.cursor);
@@ -551,8 +563,10 @@ bool partitioned_supported(const Dims& d) {
 bool tuning_valid(const cbaa_tuning* t) {
   if (!t) return true;
   const Tuning r = effective(t);
+  // seg is bounded so that the segment arithmetic of the bases and the apply
+  // (n + seg - 1, r0 + seg) stays inside 32 bits
   return r.chunk >= 1024 && r.chunk <= (1u << 22) && r.chunk % 1024 == 0 && r.seg >= 1024 &&
-         r.apply_blocks >= 1 && r.apply_blocks <= 65536;
+         r.seg <= (1u << 24) && r.apply_blocks >= 1 && r.apply_blocks <= 65536;
 }
 
 uint64_t batch_scratch_bytes(const Dims& d, const StreamSpec* specs, int k, int n_cubes,

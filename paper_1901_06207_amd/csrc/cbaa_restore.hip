@@ -39,6 +39,7 @@ struct RestoreScratch {
   uint32_t* wcnt;   // [kJoinWaves]: how many of its slots each wave filled
   uint64_t* keys;   // [capacity]: index and IP of each entry, bucket-ordered
   uint32_t* bucket; // [2][kBuckets + 1]: starts, fills
+  uint64_t* work;   // [1]: tuples the tuple check has examined (budget)
   uint64_t bytes;
 };
 
@@ -71,6 +72,7 @@ RestoreScratch carve(const Dims& d, void* base, uint64_t capacity) {
   r.wcnt = (uint32_t*)take((uint64_t)kJoinWaves * 4);
   r.keys = (uint64_t*)take(capacity * 8);
   r.bucket = (uint32_t*)take(2ull * (kBuckets + 1) * 4);
+  r.work = (uint64_t*)take(8);
   r.bytes = off;
   return r;
 }
@@ -266,7 +268,10 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
   const uint32_t i = blockIdx.y;
   const bool lead = blockIdx.z == 0;
   double e;
-  const int32_t zm = sketch_threshold(d, ones, cs, x, rule, &e);
+  int32_t zm = sketch_threshold(d, ones, cs, x, rule, &e);
+  // a cube read without this configuration's valid header restores nothing:
+  // no column is hot
+  if (stats && (stats->status & CBAA_STATUS_CONFIG)) zm = -1;
   if (lead && i == 0 && threadIdx.x == 0) {
     eps[cs] = e;
     zmax[cs] = zm;
@@ -333,13 +338,26 @@ __global__ __launch_bounds__(kPrepBlock) void k_prepare(Dims d, const uint16_t* 
   }
 }
 
-__global__ void k_reset(cbaa_restore_stats* st, uint32_t* ones, uint32_t n_ones) {
+// Zeroes the counters and the fill accumulators. With stats, it also checks
+// the headers of the cubes the restore reads (status CBAA_STATUS_CONFIG if any
+// lacks this configuration's valid one) and writes the header of the stored
+// merge, if any (valid only when every source's is). A source that is the
+// merge's destination has its header read before it is written, by the same
+// thread.
+__global__ void k_reset(Dims d, cbaa_restore_stats* st, uint32_t* ones, uint32_t n_ones,
+                        uint64_t* work, CubeSrc src, uint64_t* dst) {
   if (st && threadIdx.x == 0) {
     st->n_hosts = 0;
     st->hot_columns = 0;
     st->partial_checked = 0;
     st->tuples_checked = 0;
+    st->tuple_space = 0;
+    bool ok = true;
+    for (int j = 0; j < src.k; ++j) ok = ok && header_ok(header_of(src.p[j]), d);
+    st->status = ok ? 0u : CBAA_STATUS_CONFIG;
+    if (dst) header_set(header_of(dst), d, ok ? CBAA_CUBE_VALID : CBAA_CUBE_MIXED);
   }
+  if (work && threadIdx.x == 0) *work = 0;
   for (uint32_t i = threadIdx.x; i < n_ones; i += blockDim.x) ones[i] = 0;
 }
 
@@ -424,6 +442,8 @@ struct JoinArgs {
   uint32_t* wcnt;
   uint64_t capacity;
   cbaa_restore_stats* stats;
+  uint64_t* work;         // tuples examined so far, over all waves
+  uint64_t max_checks;    // work budget
 };
 
 // Output entry of a restored host: IP reassembled from its sketch and LP
@@ -501,10 +521,14 @@ __device__ inline void load_hot(const Dims& d, const JoinArgs& ja, uint32_t cs, 
 }
 
 // Candidates of an intermediate RA that pass the CP screen are taken kBatch
+// (BatchLen<RPL>: 2 when a column takes 8 registers per lane)
 // at a time so their column loads are in flight together; complete tuples
 // are queued kQueue<RPL> at a time (fewer when a column takes more
 // registers per lane).
-constexpr int kBatch = 4;
+template <int RPL>
+struct BatchLen {
+  static constexpr int value = RPL >= 8 ? 2 : 4;
+};
 constexpr int kListRegs = 4;
 template <int RPL>
 struct QueueLen {
@@ -528,8 +552,38 @@ struct Walk {
   uint32_t qp[Q][NRA];               // [0, nq): columns and positions (RA 0 unused)
   int nq;
   uint32_t n_partial, n_tuples;
+  uint32_t pending;                  // tuples examined since the last report
+  bool stop;                         // the work budget is spent: unwind
   Found found;
 };
+
+// Work budget, counted in tuples examined: partial tuples whose AND is
+// counted and complete CP-valid tuples (queued for the VA test and the union
+// column). At the start of every 64-candidate round of a hot list, a wave
+// that has examined kBudgetStep or more tuples since its last report adds
+// them to the shared counter; when the total passes the budget, the wave
+// stops (the rounds, the kept-candidate loop and the item loop test `stop`)
+// and the restore is flagged incomplete. A round examines at most 64 tuples
+// before the next round of some list starts, so every wave that keeps working
+// notices within kBudgetStep + 64 tuples and the grid drains soon after.
+constexpr uint32_t kBudgetStep = 256;
+template <int NRA, int RPL>
+__device__ inline void spend(const JoinArgs& ja, Walk<NRA, RPL>& w) {
+  if (w.pending < kBudgetStep) return;
+  uint64_t before = 0;
+  if (lane_id() == 0)
+    before = __hip_atomic_fetch_add(ja.work, (uint64_t)w.pending, __ATOMIC_RELAXED,
+                                    __HIP_MEMORY_SCOPE_AGENT);
+  before = ((uint64_t)__builtin_amdgcn_readfirstlane((uint32_t)(before >> 32)) << 32) |
+           (uint32_t)__builtin_amdgcn_readfirstlane((uint32_t)before);
+  if (before + w.pending > ja.max_checks) {
+    w.stop = true;
+    if (lane_id() == 0)
+      __hip_atomic_fetch_or(&ja.stats->status, (uint64_t)CBAA_STATUS_BUDGET, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+  }
+  w.pending = 0;
+}
 
 // Screens HC(LEVEL) 64 entries at a time: `round(cand, valid, base)` is
 // called with entry base + lane of the list. The first kListRegs rounds take
@@ -537,12 +591,15 @@ struct Walk {
 // register is ever picked by a run-time index), later rounds from memory.
 // HC(1) is screened only inside the item's window [b1_lo, b1_hi).
 template <int NRA, int RPL, int LEVEL, typename F>
-__device__ __attribute__((always_inline)) void for_list(const Walk<NRA, RPL>& w, F&& round) {
+__device__ __attribute__((always_inline)) void for_list(const JoinArgs& ja, Walk<NRA, RPL>& w,
+                                                        F&& round) {
   uint32_t r[kListRegs];
 #pragma unroll
   for (int k = 0; k < kListRegs; ++k) r[k] = w.reg[LEVEL][k];
   const uint32_t cnt = w.cnt[LEVEL];
   for (uint32_t base = 0; base < cnt; base += kWave) {
+    spend(ja, w);
+    if (w.stop) break;
     const uint32_t j = base + lane_id();
     uint32_t cand;
     if (base < (uint32_t)(kListRegs * kWave)) {
@@ -630,7 +687,7 @@ __device__ __attribute__((always_inline)) void extend_last(const Dims& d, const 
   const uint32_t want_lo = w.t[L - 1] >> d.ep[L - 1];      // CP of hc_{l-1}
   const uint32_t cp_mask = low_mask(d.cp[L - 1]);
   const uint32_t want_hi = w.t[0] & low_mask(d.cp[L]);     // first bits of hc_0
-  for_list<NRA, RPL, L>(w, [&](uint32_t cand, bool valid, uint32_t base) {
+  for_list<NRA, RPL, L>(ja, w, [&](uint32_t cand, bool valid, uint32_t base) {
     const bool ok = valid && (cand & cp_mask) == want_lo && (cand >> d.ep[L]) == want_hi;
     uint64_t m = __ballot(ok);
     while (m) {
@@ -654,6 +711,7 @@ __device__ __attribute__((always_inline)) void extend_last(const Dims& d, const 
       }
       w.qc[0][L] = h;
       w.qp[0][L] = base + (uint32_t)l;
+      ++w.pending;
       if (++w.nq == Q) check_queue<NRA, NVA, RPL, G>(d, ja, w);
     }
   });
@@ -664,9 +722,10 @@ __device__ __attribute__((always_inline)) void extend_last(const Dims& d, const 
 template <int NRA, int NVA, int RPL, int LEVEL, bool G>
 __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinArgs& ja, Walk<NRA, RPL>& w,
                        const Col<RPL>& acc) {
+  constexpr int kBatch = BatchLen<RPL>::value;
   const uint32_t want_lo = w.t[LEVEL - 1] >> d.ep[LEVEL - 1];
   const uint32_t cp_mask = low_mask(d.cp[LEVEL - 1]);
-  for_list<NRA, RPL, LEVEL>(w, [&](uint32_t cand, bool valid, uint32_t base) {
+  for_list<NRA, RPL, LEVEL>(ja, w, [&](uint32_t cand, bool valid, uint32_t base) {
     const bool ok = valid && (cand & cp_mask) == want_lo;
     uint64_t m = __ballot(ok);
     while (m) {
@@ -699,6 +758,7 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
         if (q >= nb) break;
         and_col(c[q], acc);
         ++w.n_partial;
+        ++w.pending;
         if ((int32_t)col_zeros<RPL>(d, c[q]) <= w.zm) keep |= 1u << q;
       }
       // the kept candidates are extended in order; each step shifts the
@@ -706,6 +766,7 @@ __device__ __attribute__((always_inline)) void extend(const Dims& d, const JoinA
       // deeper levels are emitted once, not once per slot
 #pragma unroll 1
       for (int q = 0; q < nb; ++q) {
+        if (w.stop) break;
         if (keep & 1u) {
           w.t[LEVEL] = h[0];
           w.tp[LEVEL] = pos[0];
@@ -734,6 +795,7 @@ __device__ __attribute__((always_inline)) void join_items(const Dims& d, const J
                                                           uint32_t total0, uint32_t total,
                                                           uint32_t gw, uint32_t nwaves) {
   for (uint32_t item = gw; item < total; item += nwaves) {
+    if (w.stop) break;
     const uint32_t win = item / total0, flat = item - win * total0;
     uint32_t lo = 0, hi = d.S;  // largest cs with pre[cs] <= flat
     while (hi - lo > 1) {
@@ -793,6 +855,19 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
     }
     pre[d.S] = acc;
     s_rounds = rounds;
+    if (blockIdx.x == 0) {
+      // tuples Alg. 3 would enumerate: sum over sketches of prod_i |HC(i)|
+      uint64_t space = 0;
+      for (uint32_t cs = 0; cs < d.S; ++cs) {
+        uint64_t prod = 1;
+        for (int i = 0; i < NRA; ++i) {
+          const uint64_t c = ja.hcnt[cs * NRA + i];
+          prod = (c != 0 && prod > ~0ull / c) ? ~0ull : prod * c;
+        }
+        space = space > ~0ull - prod ? ~0ull : space + prod;
+      }
+      ja.stats->tuple_space = space;
+    }
   }
   __syncthreads();
   const uint32_t total0 = pre[d.S];
@@ -803,6 +878,8 @@ __global__ __launch_bounds__(kJoinBlock) void k_join(Dims d, JoinArgs ja) {
   Walk<NRA, RPL> w;
   w.n_partial = 0;
   w.n_tuples = 0;
+  w.pending = 0;
+  w.stop = false;
   w.found.n = 0;
   if (all_fit)
     join_items<NRA, NVA, RPL, true>(d, ja, w, pre, total0, total, gw, nwaves);
@@ -1141,11 +1218,15 @@ int check_launch(const char* what) {
   return e == hipSuccess ? CBAA_OK : hip_fail(e, what);
 }
 
-// Zeroes the counters (stats may be null) and the fill accumulators, then
-// scans the cube.
+// Zeroes the counters (stats and work may be null) and the fill accumulators,
+// checks the cube's header (with stats), then scans the cube.
 int run_scan(const Dims& d, const uint64_t* cube, uint16_t* zeros, uint32_t* ones,
-             cbaa_restore_stats* stats, hipStream_t s) {
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, stats, ones, d.S * d.A);
+             cbaa_restore_stats* stats, uint64_t* work, hipStream_t s) {
+  CubeSrc one{};
+  one.p[0] = cube;
+  one.k = 1;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, d, stats, ones, d.S * d.A, work, one,
+                     (uint64_t*)nullptr);
   int rc = check_launch("reset launch");
   if (rc != CBAA_OK) return rc;
   const uint32_t half_w = d.W / 2;
@@ -1239,7 +1320,7 @@ uint64_t restore_scratch_bytes(const Dims& d, uint64_t capacity) {
 
 int launch_column_zeros(const Dims& d, const uint64_t* cube, uint16_t* zeros, uint32_t* ones,
                         hipStream_t s) {
-  return run_scan(d, cube, zeros, ones, nullptr, s);
+  return run_scan(d, cube, zeros, ones, nullptr, nullptr, s);
 }
 
 namespace {
@@ -1247,15 +1328,15 @@ namespace {
 // Everything after the column scan: thresholds, hot lists and gather, join,
 // ordering.
 int restore_after_scan(const Dims& d, const CubeSrc& cube, double x, int rule,
-                       const RestoreScratch& rs, uint64_t capacity, cbaa_host* out,
-                       cbaa_restore_stats* stats, hipStream_t s) {
+                       uint64_t max_checks, const RestoreScratch& rs, uint64_t capacity,
+                       cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s) {
   int rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, d.n_ra, kPrepParts), dim3(kPrepBlock), 0, s, d,
                      rs.zeros, rs.ones, rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats, cube,
                      rs.hcol, rs.gcap, rs.gfit);
   if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
-  JoinArgs ja{cube, rs.zeros, rs.hot, rs.hcol, rs.gfit, rs.gcap, rs.hcnt, rs.zmax, rs.eps,
-              rs.stage, rs.wbuf, rs.wcnt, capacity, stats};
+  JoinArgs ja{cube,     rs.zeros,  rs.hot,  rs.hcol, rs.gfit,  rs.gcap,  rs.hcnt, rs.zmax,
+              rs.eps,   rs.stage,  rs.wbuf, rs.wcnt, capacity, stats,    rs.work, max_checks};
   if ((rc = run_join(d, ja, s)) != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_compact, dim3(1), dim3(kCompactBlock), 0, s, rs.wbuf, rs.wcnt, stats,
                      rs.stage, capacity);
@@ -1285,20 +1366,22 @@ int restore_after_scan(const Dims& d, const CubeSrc& cube, double x, int rule,
 
 }  // namespace
 
-int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, void* scratch,
-                   uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s) {
+int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, uint64_t max_checks,
+                   void* scratch, uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats,
+                   hipStream_t s) {
   RestoreScratch rs = carve(d, scratch, capacity);
-  int rc = run_scan(d, cube, rs.zeros, rs.ones, stats, s);
+  int rc = run_scan(d, cube, rs.zeros, rs.ones, stats, rs.work, s);
   if (rc != CBAA_OK) return rc;
   CubeSrc one{};
   one.p[0] = cube;
   one.k = 1;
-  return restore_after_scan(d, one, x, rule, rs, capacity, out, stats, s);
+  return restore_after_scan(d, one, x, rule, max_checks, rs, capacity, out, stats, s);
 }
 
 int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
-                         double x, int rule, void* scratch, uint64_t capacity, cbaa_host* out,
-                         cbaa_restore_stats* stats, hipStream_t s) {
+                         double x, int rule, uint64_t max_checks, void* scratch,
+                         uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats,
+                         hipStream_t s) {
   if (k > kMergeScanSources) {   // merge in passes first, then the plain restore
     if (!dst) {
       set_error("more than %d source cubes need a destination cube", kMergeScanSources);
@@ -1306,10 +1389,14 @@ int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* sr
     }
     const int rc = launch_merge_or(d, dst, srcs, k, s);
     if (rc != CBAA_OK) return rc;
-    return launch_restore(d, dst, x, rule, scratch, capacity, out, stats, s);
+    return launch_restore(d, dst, x, rule, max_checks, scratch, capacity, out, stats, s);
   }
   RestoreScratch rs = carve(d, scratch, capacity);
-  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, stats, rs.ones, d.S * d.A);
+  CubeSrc all{};
+  for (int j = 0; j < k; ++j) all.p[j] = srcs[j];
+  all.k = k;
+  hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, d, stats, rs.ones, d.S * d.A, rs.work, all,
+                     dst);
   int rc = check_launch("reset launch");
   if (rc != CBAA_OK) return rc;
   MergeSrc ms{};
@@ -1327,14 +1414,14 @@ int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* sr
     for (int j = 0; j < k; ++j) cs.p[j] = srcs[j];
     cs.k = k;
   }
-  return restore_after_scan(d, cs, x, rule, rs, capacity, out, stats, s);
+  return restore_after_scan(d, cs, x, rule, max_checks, rs, capacity, out, stats, s);
 }
 
 int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
                     double* est, uint16_t* zeros, uint16_t* layer_zeros, void* scratch,
                     hipStream_t s) {
   RestoreScratch rs = carve(d, scratch, 0);
-  int rc = run_scan(d, cube, rs.zeros, rs.ones, nullptr, s);
+  int rc = run_scan(d, cube, rs.zeros, rs.ones, nullptr, nullptr, s);
   if (rc != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, 1), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
                      rs.eps, rs.zmax, rs.hcnt, (uint16_t*)nullptr, 1.0, CBAA_THR_THM2,
@@ -1347,7 +1434,7 @@ int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, 
 int launch_features(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,
                     uint32_t F, float* x, void* scratch, hipStream_t s) {
   RestoreScratch rs = carve(d, scratch, 0);
-  int rc = run_scan(d, cube, rs.zeros, rs.ones, nullptr, s);
+  int rc = run_scan(d, cube, rs.zeros, rs.ones, nullptr, nullptr, s);
   if (rc != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_prepare, dim3(d.S, 1), dim3(kPrepBlock), 0, s, d, rs.zeros, rs.ones,
                      rs.eps, rs.zmax, rs.hcnt, (uint16_t*)nullptr, 1.0, CBAA_THR_THM2,

@@ -23,6 +23,26 @@ __global__ __launch_bounds__(kBlock) void k_fill_zero(uint4* p, uint64_t n16) {
     p[i] = make_uint4(0u, 0u, 0u, 0u);
 }
 
+// A new cube: zero bits, and a whole valid header (reserved words zero).
+__global__ __launch_bounds__(kBlock) void k_cube_init(Dims d, uint64_t* bits) {
+  uint4* p = (uint4*)bits;
+  const uint64_t n16 = d.words / 2;
+  const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
+  for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
+    p[i] = make_uint4(0u, 0u, 0u, 0u);
+  if (blockIdx.x == 0 && threadIdx.x < kHeaderWords) {
+    uint64_t* h = header_of(bits);
+    if (threadIdx.x == 0) header_set(h, d, CBAA_CUBE_VALID);
+    if (threadIdx.x >= 4) h[threadIdx.x] = 0;
+  }
+}
+
+// The direct path's cubes keep a valid header only if they have one.
+__global__ void k_touch_headers(Dims d, uint64_t* c0, uint64_t* c1) {
+  if (threadIdx.x == 0 && c0) header_touch(c0, d);
+  if (threadIdx.x == 1 && c1) header_touch(c1, d);
+}
+
 // Sets the A bits of one (host, peer) pair: bit H_bv(peer) of the host's
 // column in every array of its sketch. 32-bit no-return atomic OR on the half
 // of the 64-bit word that holds the bit.
@@ -62,8 +82,17 @@ struct MergeSources {
 };
 
 // dst = (accumulate ? dst : 0) | OR of k <= 8 sources, 16 bytes per lane.
-__global__ __launch_bounds__(kBlock) void k_merge_or(uint4* dst, MergeSources s, int k,
+// The first thread also writes dst's header: valid only if every source (and,
+// when accumulating, dst's own earlier pass) carries this configuration's
+// valid header. A source that is dst is placed first, and its header is read
+// before it is written, by the same thread.
+__global__ __launch_bounds__(kBlock) void k_merge_or(Dims d, uint4* dst, MergeSources s, int k,
                                                      uint64_t n16, int accumulate) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    bool ok = !accumulate || header_ok(header_of((const uint64_t*)dst), d);
+    for (int j = 0; j < k; ++j) ok = ok && header_ok(header_of((const uint64_t*)s.p[j]), d);
+    header_set(header_of((uint64_t*)dst), d, ok ? CBAA_CUBE_VALID : CBAA_CUBE_MIXED);
+  }
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
     uint4 v = accumulate ? dst[i] : make_uint4(0u, 0u, 0u, 0u);
@@ -106,8 +135,17 @@ int launch_fill_zero(uint64_t* p, uint64_t words, hipStream_t s) {
   return e == hipSuccess ? CBAA_OK : hip_fail(e, "fill kernel launch");
 }
 
+int launch_cube_init(const Dims& d, uint64_t* bits, hipStream_t s) {
+  hipLaunchKernelGGL(k_cube_init, dim3(grid_for(d.words / 2, kBlock)), dim3(kBlock), 0, s, d, bits);
+  hipError_t e = hipGetLastError();
+  return e == hipSuccess ? CBAA_OK : hip_fail(e, "cube init launch");
+}
+
 int launch_update_direct(const Dims& d, uint64_t* cube0, uint64_t* cube1, const uint32_t* pairs,
                          uint64_t n, int side, hipStream_t s) {
+  hipLaunchKernelGGL(k_touch_headers, dim3(1), dim3(64), 0, s, d, cube0, cube1);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(e, "header launch");
   if (cube1)
     return dispatch_direct<true>(d, (uint32_t*)cube0, (uint32_t*)cube1, (const uint2*)pairs, n,
                                  CBAA_SIDE_SRC, s);
@@ -132,8 +170,8 @@ int launch_merge_or(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, i
     MergeSources ms{};
     int m = k - base < 8 ? k - base : 8;
     for (int j = 0; j < m; ++j) ms.p[j] = (const uint4*)ord[base + j];
-    hipLaunchKernelGGL(k_merge_or, dim3(grid_for(n16, kBlock)), dim3(kBlock), 0, s, (uint4*)dst, ms,
-                       m, n16, base > 0 ? 1 : 0);
+    hipLaunchKernelGGL(k_merge_or, dim3(grid_for(n16, kBlock)), dim3(kBlock), 0, s, d, (uint4*)dst,
+                       ms, m, n16, base > 0 ? 1 : 0);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) rc = hip_fail(e, "merge kernel launch");
   }

@@ -37,8 +37,8 @@ def test_default_config_and_sizes():
     c = cbaa.cbaa_config_default()
     assert cbaa.Config.from_dict(default_params()) == c
     assert cbaa.cbaa_config_validate(c) == 0
-    assert cbaa.cbaa_cube_bytes(c) == 1 << 27
-    assert cbaa.cbaa_abi_version() == 1
+    assert cbaa.cbaa_cube_bytes(c) == (1 << 27) + 256   # 256-byte header + the printed 128 MB
+    assert cbaa.cbaa_abi_version() == 2
     assert cbaa.cbaa_restore_scratch_bytes(c, 1000) > cbaa.cbaa_restore_scratch_bytes(c, 0)
 
 
@@ -72,9 +72,76 @@ def test_bad_arguments_rejected_before_any_device_work():
     arr = (C.c_void_p * 1)(None)
     assert lib.cbaa_merge_or(C.byref(c), 16, arr, 1, None) == cbaa.CBAA_EINVAL
     assert lib.cbaa_merge_or(C.byref(c), 16, arr, 0, None) == cbaa.CBAA_EINVAL
-    assert lib.cbaa_restore(C.byref(c), 16, 1024.0, 5, 256, 1 << 30, 16, 1, 16, None) == cbaa.CBAA_EINVAL
-    assert lib.cbaa_restore(C.byref(c), 16, -1.0, 0, 256, 1 << 30, 16, 1, 16, None) == cbaa.CBAA_EINVAL
-    assert lib.cbaa_restore(C.byref(c), 16, 1024.0, 0, 256, 10, 16, 1, 16, None) == cbaa.CBAA_ESCRATCH
+    assert lib.cbaa_restore(C.byref(c), 16, 1024.0, 5, 0, 256, 1 << 30, 16, 1, 16, None) == cbaa.CBAA_EINVAL
+    assert lib.cbaa_restore(C.byref(c), 16, -1.0, 0, 0, 256, 1 << 30, 16, 1, 16, None) == cbaa.CBAA_EINVAL
+    assert lib.cbaa_restore(C.byref(c), 16, 1024.0, 0, 0, 256, 10, 16, 1, 16, None) == cbaa.CBAA_ESCRATCH
+    assert lib.cbaa_cube_check(C.byref(c), None, None) == cbaa.CBAA_EINVAL
     bad = cbaa.Config(cl_bs=(3, 14, 23)).to_c()
     assert lib.cbaa_cube_init(C.byref(bad), 16, None) == cbaa.CBAA_ECONFIG
     assert cbaa.cbaa_cube_bytes(cbaa.Config(cl_bs=(3, 14, 23))) == 0
+
+
+def test_merge_needs_a_destination():
+    """cbaa_merge_or stores the OR: a null destination is refused before any
+    launch (cbaa_merge_restore alone may leave the merge unstored)."""
+    import ctypes as C
+    from paper_1901_06207_amd import cbaa
+    lib = cbaa.lib()
+    c = cbaa.Config().to_c()
+    srcs = (C.c_void_p * 1)(16)
+    assert lib.cbaa_merge_or(C.byref(c), None, srcs, 1, None) == cbaa.CBAA_EINVAL
+    assert "destination" in cbaa.cbaa_last_error()
+    many = (C.c_void_p * 17)(*([16] * 17))
+    assert lib.cbaa_merge_restore(C.byref(c), None, many, 17, 1024.0, 0, 0, 256, 1 << 30, None, 0,
+                                  16, None) == cbaa.CBAA_EINVAL
+    with pytest.raises(ValueError):
+        cbaa.cbaa_merge_or(cbaa.Config(), None, [])
+
+
+def test_tuning_bounds():
+    """seg_records above 2^24 would wrap the 32-bit segment arithmetic; such a
+    tuning is refused by the size query and by the update itself."""
+    import ctypes as C
+    from paper_1901_06207_amd import cbaa
+    lib = cbaa.lib()
+    c = cbaa.Config().to_c()
+    table = (cbaa.cbaa_stream_batch * 1)()
+    table[0].d_pairs, table[0].n_pairs, table[0].d_cube = 16, 1 << 20, 256
+    ok = cbaa.cbaa_tuning(0, 1 << 24, 0, 0)
+    bad = cbaa.cbaa_tuning(0, 1 << 31, 0, 0)
+    assert lib.cbaa_update_batch_scratch_bytes(C.byref(c), table, 1, C.byref(ok)) > 0
+    assert lib.cbaa_update_batch_scratch_bytes(C.byref(c), table, 1, C.byref(bad)) == 0
+    assert lib.cbaa_update_batch(C.byref(c), table, 1, C.byref(bad), 256, 1 << 40,
+                                 None) == cbaa.CBAA_EINVAL
+    small = cbaa.cbaa_tuning(0, 512, 0, 0)
+    assert lib.cbaa_update_batch(C.byref(c), table, 1, C.byref(small), 256, 1 << 40,
+                                 None) == cbaa.CBAA_EINVAL
+
+
+def _fnv1a64_words(words):
+    """64-bit FNV-1a over the little-endian bytes of 32-bit words."""
+    h = 0xCBF29CE484222325
+    for w in words:
+        for byte in int(w).to_bytes(4, "little"):
+            h ^= byte
+            h = (h * 0x100000001B3) & 0xFFFFFFFFFFFFFFFF
+    return h
+
+
+def test_config_hash_definition():
+    """The header's configuration hash is FNV-1a over the defined fields in
+    the documented order; fields beyond the array counts do not enter it."""
+    from paper_1901_06207_amd import cbaa
+    for p in [default_params(), *TINY_CONFIGS.values()]:
+        A = p["n_ra"] + p["n_va"]
+        words = [p["r"], p["n_ra"], p["n_va"], p["log2_g"], *p["cbn"][:A], *p["cl_bs"][:p["n_ra"]],
+                 p["seed_mangle"], p["seed_bv"], *p["seed_va"][:p["n_va"]]]
+        assert cbaa.cbaa_config_hash(p) == _fnv1a64_words(words), p
+    base = default_params()
+    unused = dict(base, seed_va=[base["seed_va"][0], 12345], cbn=list(base["cbn"]) + [7, 7])
+    assert cbaa.cbaa_config_hash(unused) == cbaa.cbaa_config_hash(base)
+    hashes = {cbaa.cbaa_config_hash(dict(base, seed_bv=base["seed_bv"] + 1)),
+              cbaa.cbaa_config_hash(dict(base, cl_bs=[4, 12, 20])),
+              cbaa.cbaa_config_hash(dict(base, log2_g=11)), cbaa.cbaa_config_hash(base)}
+    assert len(hashes) == 4
+    assert cbaa.cbaa_config_hash(dict(base, r=9)) == 0

@@ -280,9 +280,9 @@ def test_restore_saturated_host(cb):
     assert got["flags"][got["ip"] == host][0] == cb.FLAG_SATURATED
 
 
-def _cube_from_numpy(cube_np):
-    import torch
-    return torch.from_numpy(np.ascontiguousarray(cube_np).view(np.int64)).cuda()
+def _cube_from_numpy(cb, p, cube_np):
+    """A device cube with a valid header of p holding the oracle's bits."""
+    return cb.cube_from_bits(p, cube_np)
 
 
 def _set_columns(p, cube_np, cs, a, cols):
@@ -305,7 +305,7 @@ def test_restore_long_hot_list_on_the_trace_cube(cb):
     cube_np = O.cube_of(p, t.pairs, 0).copy()
     _set_columns(p, cube_np, 3, 0, np.arange(1000, 2500))
     _say("long hot list")
-    got, st = cb.restore(p, _cube_from_numpy(cube_np), 1024.0)
+    got, st = cb.restore(p, _cube_from_numpy(cb, p, cube_np), 1024.0)
     want, wst = O.restore(p, cube_np, 1024.0)
     assert st["hot_columns"] == wst["hot_columns"] and wst["hot_columns"] > 1500
     _assert_hosts_equal(got, want)
@@ -324,7 +324,7 @@ def test_restore_tens_of_thousands_of_hosts(cb):
     _set_columns(p, cube_np, 0, 2, [1234])
     _set_columns(p, cube_np, 0, 3, np.arange(4096))
     _say("65536 hosts")
-    got, st = cb.restore(p, _cube_from_numpy(cube_np), 1024.0)
+    got, st = cb.restore(p, _cube_from_numpy(cb, p, cube_np), 1024.0)
     want, _ = O.restore(p, cube_np, 1024.0)
     assert want.size == 65536
     _assert_hosts_equal(got, want)
@@ -400,7 +400,7 @@ def test_merge_restore_without_destination_long_hot_list(cb):
     _set_columns(p, cube_np, 3, 0, np.arange(1000, 2500))
     rng = np.random.default_rng(3)
     who = rng.integers(0, 3, cube_np.size)   # every word of the cube goes to one router
-    srcs = [_cube_from_numpy(np.where(who == i, cube_np, np.uint64(0))) for i in range(3)]
+    srcs = [_cube_from_numpy(cb, p, np.where(who == i, cube_np, np.uint64(0))) for i in range(3)]
     _say("merge restore, no destination, long hot list")
     got, st = _merge_restore(cb, p, None, srcs)
     want, wst = O.restore(p, cube_np, 1024.0)
@@ -442,9 +442,15 @@ def core_edge():
     return tracegen.window_core_edge(11)
 
 
-def test_full_core_edge_window(cb, core_edge):
-    """The 64Mi-packet window in the benchmark's configuration: both cubes
-    bit-exact and both restored lists equal to the oracle's."""
+@pytest.fixture(scope="module")
+def core_edge_cubes(core_edge):
+    """The oracle's source- and destination-keyed cubes of the window."""
+    return [O.cube_of(default_params(), core_edge.pairs, side) for side in (0, 1)]
+
+
+def test_full_core_edge_window(cb, core_edge, core_edge_cubes):
+    """The 64Mi-packet window through cbaa_update2 and cbaa_restore: both
+    cubes bit-exact and both restored lists equal to the oracle's."""
     import torch
     p = default_params()
     t = core_edge
@@ -454,9 +460,77 @@ def test_full_core_edge_window(cb, core_edge):
     cb.cbaa_update2(p, a, b, cb.pairs_to_device(t.pairs), scratch)
     torch.cuda.synchronize()
     for side, cube in ((0, a), (1, b)):
-        want_cube = O.cube_of(p, t.pairs, side)
+        want_cube = core_edge_cubes[side]
         assert np.array_equal(cb.cube_to_numpy(cube), want_cube)
         got, st = cb.restore(p, cube, 1024.0)
         want, _ = O.restore(p, want_cube, 1024.0)
         _say("core-edge restore side", side, got.size, st)
         _assert_hosts_equal(got, want)
+
+
+def test_benchmark_step_on_core_edge_window(cb, core_edge, core_edge_cubes):
+    """The benchmark's timed step at full size, call for call: the window
+    split over two edge routers (seed 11), one cbaa_update_batch of both
+    routers' streams flagged fresh into cubes holding stale bits, then per side
+    cbaa_merge_restore with no destination (the merged cube not stored). The
+    router cubes OR to the oracle's cube of the window, and the restored lists
+    are the oracle's under both threshold rules."""
+    import torch
+    p = default_params()
+    t = core_edge
+    parts = tracegen.split_routers(t.pairs, 2, seed=11)
+    local = []
+    for _ in parts:
+        a, b = cb.new_cube(p, init=False), cb.new_cube(p, init=False)
+        a.fill_(-1)
+        b.fill_(-1)
+        local.append((a, b))
+    table = [(cb.pairs_to_device(q), a, b, cb.SIDE_SRC, cb.BATCH_FRESH)
+             for q, (a, b) in zip(parts, local)]
+    scratch = cb.scratch_tensor(cb.cbaa_update_batch_scratch_bytes(p, table))
+    _say("benchmark step, update", [len(q) for q in parts])
+    cb.cbaa_update_batch(p, table, scratch)
+    torch.cuda.synchronize()
+    cap = 1 << 14
+    rs = cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, cap))
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    st = cb.stats_tensor()
+    for side in (0, 1):
+        merged = cb.cube_to_numpy(local[0][side]) | cb.cube_to_numpy(local[1][side])
+        assert np.array_equal(merged, core_edge_cubes[side]), side
+        del merged
+        for rule in (cb.THR_THM2, cb.THR_PAPER):
+            _say("benchmark step, window end", side, rule)
+            cb.cbaa_merge_restore(p, None, [x[side] for x in local], 1024.0, rule, rs, out, cap, st)
+            s = cb.stats_dict(st)
+            assert s["status"] == 0 and s["n_hosts"] <= cap
+            got = cb.host_list(out, s["n_hosts"])
+            want, wst = O.restore(p, core_edge_cubes[side], 1024.0, rule)
+            _say("  hosts", got.size, "tuple space", s["tuple_space"], wst)
+            assert s["tuple_space"] == wst["tuples"]
+            _assert_hosts_equal(got, want)
+
+
+# ---------------------------------------------------------------- g = 8192
+
+@pytest.mark.parametrize("path", PATHS)
+def test_g8192_update_restore_estimate(cb, path):
+    """Columns of 8192 bits (128 row blocks; two 64-bit words per lane in the
+    join and the estimate): cube, restored list and estimates against the
+    oracle."""
+    p = dict(default_params(), log2_g=13)
+    t = tracegen.window_small(6)
+    _say("g8192", path)
+    cube = _gpu_cube(cb, p, t.pairs, 0, path)
+    want_cube = O.cube_of(p, t.pairs, 0)
+    assert np.array_equal(cb.cube_to_numpy(cube), want_cube)
+    for rule in (cb.THR_THM2, cb.THR_PAPER):
+        got, st = cb.restore(p, cube, 1024.0, rule)
+        want, _ = O.restore(p, want_cube, 1024.0, rule)
+        assert got.size > 10
+        _assert_hosts_equal(got, want)
+    hosts = np.concatenate([t.planted_ips, t.bg_ips[:3000]])
+    est, zeros = cb.estimate(p, cube, hosts)
+    west, wz, _ = O.estimate(p, want_cube, hosts)
+    assert np.array_equal(zeros, wz)
+    assert np.all(np.abs(est - west) <= EST_RTOL * np.maximum(1.0, west))
