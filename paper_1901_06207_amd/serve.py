@@ -130,7 +130,7 @@ class Server:
         splits.append([max(1, max_pairs // k)] * k)
         best = 0
         for sizes in splits:
-            table = cbaa._stream_table([(dummy, a, b, cbaa.SIDE_SRC)] * len(sizes))
+            table = cbaa._stream_table(self.cfg, [(dummy, a, b, cbaa.SIDE_SRC)] * len(sizes))
             for i, n in enumerate(sizes):
                 table[i].n_pairs = n
             need = cbaa.lib().cbaa_update_batch_scratch_bytes(
