@@ -87,6 +87,7 @@ def test_admission_by_memory_and_latency(cb):
     assert res["packets"] == sum(len(q) for _, q, _ in chunks)
     assert 0 < srv.alloc.peak <= budget
     assert res["p99_ms"] >= res["p50_ms"] > 0
-    # next window starts from zeroed cubes
+    # next window starts from emptied cubes that carry a valid header
     for a, _ in srv.cubes:
-        assert int(a.abs().sum()) == 0
+        assert int(a[cb.HEADER_WORDS:].abs().sum()) == 0
+        assert cb.cbaa_cube_check(p, a) == 0
