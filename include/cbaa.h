@@ -315,6 +315,25 @@ int cbaa_merge_restore(const cbaa_config* h_cfg, void* d_dst, const void* const*
                        uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
                        cbaa_restore_stats* d_stats, void* stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc):
+ * cbaa_merge_restore without a scratch argument. Its scratch is an array of
+ * CBAA_NOALLOC_SCRATCH_BYTES inside the library, one copy per device, held
+ * from the first call on that device until the process ends; the call itself
+ * allocates nothing, host or device (at most 64 sources, kept on the stack).
+ * The first call on a device resolves the array's address (make it outside
+ * graph capture). Arguments, results and asynchrony are those of
+ * cbaa_merge_restore. CBAA_ESCRATCH when cbaa_restore_scratch_bytes(cfg,
+ * capacity) exceeds the array (at the paper's dimensions that is a capacity
+ * above about 1.5 million hosts). Every call on a device shares that device's
+ * array, which keeps the last call's contents: calls that overlap on one device
+ * (other streams, other threads) race and must be serialised by the caller. */
+#define CBAA_NOALLOC_SCRATCH_BYTES (64ull << 20)
+int cbaa_merge_restore_noalloc(const cbaa_config* h_cfg, void* d_dst, const void* const* h_srcs,
+                               int k, double theta, int thr_rule, uint64_t max_checks,
+                               cbaa_host* d_out, uint64_t capacity, cbaa_restore_stats* d_stats,
+                               void* stream);
+
 /* Thm. 2 estimate for given inner IPs: d_est[k] (double), d_zeros[k] (Z of
  * the union column) and, if d_layer_zeros is not NULL, the zero count of each
  * of the host's n_ra+n_va columns at d_layer_zeros[k*A + a] (uint16). eps is

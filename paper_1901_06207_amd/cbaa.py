@@ -68,6 +68,7 @@ class cbaa_tuning(C.Structure):
                 ("apply_blocks", C.c_uint32), ("reserved", C.c_uint32)]
 
 
+NOALLOC_SCRATCH_BYTES = 64 << 20
 MAX_BATCH = 32
 
 HOST_DTYPE = np.dtype([("ip", "<u4"), ("zeros", "<u2"), ("cs", "u1"), ("flags", "u1"),
@@ -160,6 +161,8 @@ def lib():
         "cbaa_estimate": (i32, [cfgp, vp, vp, u64, vp, vp, vp, vp, u64, vp]),
         "cbaa_merge_restore": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, u64, vp, u64, vp, u64,
                                      vp, vp]),
+        "cbaa_merge_restore_noalloc": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, u64, vp, u64,
+                                             vp, vp]),
         "cbaa_mlp_param_count": (C.c_uint32, [C.c_uint32]),
         "cbaa_mlp_init": (i32, [C.c_uint32, C.c_uint32, i32, vp, vp, vp]),
         "cbaa_mlp_features": (i32, [cfgp, vp, vp, u64, C.c_uint32, vp, vp, u64, vp]),
@@ -380,6 +383,20 @@ def cbaa_merge_restore(cfg, dst: Optional[torch.Tensor], srcs: Sequence[torch.Te
                                     else None, capacity,
                                     _dev_ptr(stats, "stats", STATS_BYTES), _stream(stream)),
            "cbaa_merge_restore")
+
+
+def cbaa_merge_restore_noalloc(cfg, dst: Optional[torch.Tensor], srcs: Sequence[torch.Tensor],
+                               theta: float, rule: int, out: Optional[torch.Tensor],
+                               capacity: int, stats: torch.Tensor, stream=None,
+                               max_checks: int = 0) -> None:
+    """cbaa_merge_restore on the library's own per-device scratch array."""
+    arr = (C.c_void_p * len(srcs))(*[_cube_ptr(cfg, x, "src") for x in srcs])
+    _check(lib().cbaa_merge_restore_noalloc(
+        C.byref(_cfg(cfg)), _cube_ptr(cfg, dst, "dst") if dst is not None else None, arr,
+        len(srcs), float(theta), rule, max_checks,
+        _dev_ptr(out, "out", capacity * HOST_BYTES) if capacity else None, capacity,
+        _dev_ptr(stats, "stats", STATS_BYTES), _stream(stream)),
+        "cbaa_merge_restore_noalloc")
 
 
 def cbaa_estimate(cfg, cube: torch.Tensor, hosts: torch.Tensor, est: torch.Tensor,

@@ -7,6 +7,8 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "../../include/cbaa_mlp.h"
 #include "cbaa_internal.hpp"
 
@@ -356,11 +358,12 @@ int cbaa_restore(const cbaa_config* cfg, const void* d_cube, double theta, int t
                         d_out, d_stats, (hipStream_t)stream);
 }
 
-int cbaa_merge_restore(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
-                       double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
-                       uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
-                       cbaa_restore_stats* d_stats, void* stream) {
-  CHECK_DIMS(cfg, d);
+// Argument checks and launch of the window end, shared by cbaa_merge_restore
+// (caller's scratch) and cbaa_merge_restore_noalloc (the library's array).
+static int merge_restore_checked(const Dims& d, void* d_dst, const void* const* h_srcs, int k,
+                                 double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
+                                 uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
+                                 cbaa_restore_stats* d_stats, void* stream) {
   // a null destination (merge not stored) is served by the one-pass scan,
   // which takes up to 16 sources
   REQUIRE(((uintptr_t)d_dst & 15u) == 0, "destination must be 16-byte aligned");
@@ -389,6 +392,80 @@ int cbaa_merge_restore(const cbaa_config* cfg, void* d_dst, const void* const* h
                                       d_scratch, capacity, d_out, d_stats, (hipStream_t)stream);
   if (b != stack) delete[] b;
   return rc;
+}
+
+int cbaa_merge_restore(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
+                       double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
+                       uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
+                       cbaa_restore_stats* d_stats, void* stream) {
+  CHECK_DIMS(cfg, d);
+  return merge_restore_checked(d, d_dst, h_srcs, k, theta, thr_rule, max_checks, d_scratch,
+                               scratch_bytes, d_out, capacity, d_stats, stream);
+}
+
+}  // extern "C"
+
+// Scratch of cbaa_merge_restore_noalloc. Each device holds its own copy of
+// this array from the library's first use on it until the process ends. In
+// host code the name is only a host-side stand-in, never a device address:
+// the address comes from hipGetSymbolAddress, resolved once per device with
+// that device current, and only that address is handed to kernels.
+static __device__ __align__(256) uint64_t g_noalloc_scratch[CBAA_NOALLOC_SCRATCH_BYTES / 8];
+
+namespace {
+
+constexpr int kNoAllocDevices = 64;
+std::mutex g_noalloc_mu;
+void* g_noalloc_ptr[kNoAllocDevices];
+
+// Device address of the current device's copy of g_noalloc_scratch.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+  if (dev < 0 || dev >= kNoAllocDevices) {
+    set_error("device %d beyond the %d the no-allocation scratch table covers", dev, kNoAllocDevices);
+    return CBAA_EINVAL;
+  }
+  std::lock_guard<std::mutex> lock(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    e = hipGetSymbolAddress(&p, HIP_SYMBOL(g_noalloc_scratch));
+    if (e != hipSuccess) return hip_fail(e, "hipGetSymbolAddress(no-allocation scratch)");
+    if (!p) {
+      set_error("hipGetSymbolAddress returned a null address for the no-allocation scratch");
+      return CBAA_EHIP;
+    }
+    g_noalloc_ptr[dev] = p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return CBAA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int cbaa_merge_restore_noalloc(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs,
+                               int k, double theta, int thr_rule, uint64_t max_checks,
+                               cbaa_host* d_out, uint64_t capacity, cbaa_restore_stats* d_stats,
+                               void* stream) {
+  CHECK_DIMS(cfg, d);
+  // the source table stays on the stack: nothing on this path allocates
+  REQUIRE(k <= 64, "at most 64 source cubes");
+  REQUIRE(capacity < (1ull << 32), "capacity must be below 2^32");
+  const uint64_t need = restore_scratch_bytes(d, capacity);
+  if (need > CBAA_NOALLOC_SCRATCH_BYTES) {
+    set_error("this configuration and capacity need %llu bytes of scratch, above the %llu of "
+              "the no-allocation entry point; use cbaa_merge_restore with a caller buffer",
+              (unsigned long long)need, (unsigned long long)CBAA_NOALLOC_SCRATCH_BYTES);
+    return CBAA_ESCRATCH;
+  }
+  void* scratch = nullptr;
+  const int rc = noalloc_scratch(&scratch);
+  if (rc != CBAA_OK) return rc;
+  return merge_restore_checked(d, d_dst, h_srcs, k, theta, thr_rule, max_checks, scratch,
+                               CBAA_NOALLOC_SCRATCH_BYTES, d_out, capacity, d_stats, stream);
 }
 
 int cbaa_estimate(const cbaa_config* cfg, const void* d_cube, const uint32_t* d_hosts, uint64_t n,

@@ -98,6 +98,25 @@ def test_merge_needs_a_destination():
         cbaa.cbaa_merge_or(cbaa.Config(), None, [])
 
 
+def test_noalloc_limits_checked_before_any_device_call():
+    """The no-allocation window end refuses, on the host, a capacity whose
+    scratch exceeds its array and a source table it could not keep on the
+    stack."""
+    import ctypes as C
+    from paper_1901_06207_amd import cbaa
+    lib = cbaa.lib()
+    c = cbaa.Config().to_c()
+    one = (C.c_void_p * 1)(256)
+    cap = 4_000_000
+    assert cbaa.cbaa_restore_scratch_bytes(cbaa.Config(), cap) > cbaa.NOALLOC_SCRATCH_BYTES
+    assert lib.cbaa_merge_restore_noalloc(C.byref(c), None, one, 1, 1024.0, 0, 0, 256, cap, 256,
+                                          None) == cbaa.CBAA_ESCRATCH
+    assert "no-allocation" in cbaa.cbaa_last_error()
+    many = (C.c_void_p * 65)(*([256] * 65))
+    assert lib.cbaa_merge_restore_noalloc(C.byref(c), 256, many, 65, 1024.0, 0, 0, 256, 16, 256,
+                                          None) == cbaa.CBAA_EINVAL
+
+
 def test_tuning_bounds():
     """seg_records above 2^24 would wrap the 32-bit segment arithmetic; such a
     tuning is refused by the size query and by the update itself."""
