@@ -78,8 +78,11 @@ def parse():
     ap.add_argument("--no-learned", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="packets of the window the CPU oracle step is timed on (0 = all)")
-    ap.add_argument("--workload", choices=["core-edge", "batched"], default="core-edge",
-                    help="batched: 32 router streams of 1M-64M packets in one graph replay")
+    ap.add_argument("--workload", choices=["core-edge", "batched", "sweep"], default="core-edge",
+                    help="batched: 32 router streams of 1M-64M packets in one graph replay; "
+                         "sweep: accuracy of the restored lists over r, g and the threshold rule")
+    ap.add_argument("--sweep-windows", default="small:1,2,3;core-edge:11,12,13",
+                    help="windows of the sweep: kind:seeds;kind:seeds")
     ap.add_argument("--streams", type=int, default=32)
     ap.add_argument("--store-merged", action="store_true",
                     help="the window end also stores each side's merged (global) cube")
@@ -114,6 +117,8 @@ def main():
         calibrate_copy(dev)
     if args.workload == "batched":
         return bench_batched(cfg, dev, args)
+    if args.workload == "sweep":
+        return bench_sweep(dev, args)
 
     t0 = time.time()
     trace = tracegen.window_core_edge(args.seed, scale=args.scale)
@@ -290,6 +295,18 @@ def main():
               "bitsets_per_window": int(bitsets)}
     atomic["ratio"] = round(atomic["partitioned_bitset_gops"] / atomic["direct_atomic_gops"], 2)
     roofline["atomic"] = atomic
+    # measured ceilings: the update against a streaming copy of this GPU, and
+    # the bit-set rate against random atomics into as many bytes as the
+    # window's router cubes (the one-thread-per-packet scheme's ceiling)
+    ceil = measure_ceilings(dev, stream)
+    roofline["ceilings"] = ceil
+    roofline["frac_of_measured_copy"] = round(achieved / ceil["hbm_copy_gbs"], 4)
+    cube_mib = 2 * len(parts) * cube_bytes / 2 ** 20
+    ceil_key = "atomic_or_gops_128MiB" if cube_mib <= 192 else "atomic_or_gops_512MiB"
+    atomic["ceiling_gops"] = ceil[ceil_key]
+    atomic["direct_ceiling_gpkt_s"] = round(ceil[ceil_key] / (2 * n_arr), 3)
+    atomic["update_over_direct_ceiling"] = round(
+        atomic["partitioned_bitset_gops"] / ceil[ceil_key], 2)
     # restore's scan (per-column zeros of one 128 MiB cube) against HBM
     zb = torch.empty(cbaa.cbaa_restore_scratch_bytes(cfg, 0), dtype=torch.uint8, device=dev)
     ones_t = torch.empty(4096, dtype=torch.int32, device=dev)
@@ -304,6 +321,21 @@ def main():
     scan_gbs = cube_bytes / (float(np.median(s_ms[1:])) * 1e-3) / 1e9
     scan = {"cube_bytes": int(cube_bytes), "ms": round(float(np.median(s_ms[1:])), 4),
             "achieved_gbs": round(scan_gbs, 1), "frac": round(scan_gbs / HBM_PEAK_GBS, 4)}
+
+    # the restored lists of the step (graph replay) against the window's exact
+    # per-host counts, per side (the generator's construction counts: every
+    # peer of a host is a distinct address, pinned equal to a sort-unique count)
+    accuracy = {}
+    for side, name in ((0, "source_keyed"), (1, "destination_keyed")):
+        lst = ref_lists[side].numpy().view(cbaa.HOST_DTYPE)
+        hosts, counts = tracegen.construction_truth(trace, side)
+        accuracy[name] = {k: (round(v, 6) if isinstance(v, float) else v)
+                          for k, v in detection_accuracy(lst["ip"], lst["est"], hosts, counts,
+                                                         args.theta).items()}
+        del hosts, counts
+    accuracy["rule"] = "THM2"
+    accuracy["note"] = ("restored lists of the timed step scored against exact per-host "
+                        "distinct-peer counts (Sec. 5.2 FNR, FPR over |H|, FTR)")
 
     serving = None if args.no_serve else bench_serving(cfg, dev, args)
     learned = None if args.no_learned else bench_learned(cfg, trace, g_src, local, dev, args)
@@ -356,6 +388,7 @@ def main():
             "super_hosts": {"source_keyed": n_found[0], "destination_keyed": n_found[1]},
         },
         "roofline": roofline,
+        "accuracy": accuracy,
         "serving": serving,
         "learned": learned,
         "cpu_baseline": cpu,
@@ -364,6 +397,99 @@ def main():
         out["autotune"] = {"best": tune_info["best"], "best_ms": round(tune_info["best_ms"], 4),
                            "default_ms": round(tune_info["default_ms"], 4)}
     print(json.dumps(out), flush=True)
+
+
+def detection_accuracy(ips, est, hosts, counts, theta, hosts_sorted=False):
+    """Sec. 5.2's rates of a restored list against exact per-host distinct-peer
+    counts: H = hosts with at least theta peers; FNR = |H minus R| / |H|; FPR =
+    |{h in R : |OP(h)| < theta}| / |H| (the paper's denominators; a restored
+    address never seen as a host counts as a false positive); FTR = FNR + FPR;
+    also precision and recall, and the relative error of the estimate on the
+    true super hosts that were restored. `hosts_sorted`: hosts are ascending
+    (sort once, score many lists)."""
+    import numpy as np
+    found = np.asarray(ips, np.uint32)
+    found_est = np.asarray(est, np.float64)
+    hosts = np.asarray(hosts, np.uint32)
+    counts = np.asarray(counts, np.int64)
+    if not hosts_sorted:
+        order = np.argsort(hosts, kind="stable")
+        hosts, counts = hosts[order], counts[order]
+    n_true = int(np.count_nonzero(counts >= theta))
+    # the count of every restored address (0 when it never appears as a host)
+    cnt = np.zeros(found.size, np.int64)
+    if found.size and hosts.size:
+        pos = np.minimum(np.searchsorted(hosts, found), hosts.size - 1)
+        hit = hosts[pos] == found
+        cnt[hit] = counts[pos[hit]]
+    tp = int(np.count_nonzero(cnt >= theta))
+    fp = int(found.size - tp)
+    fn = n_true - tp
+    nh = max(n_true, 1)
+    rel = np.abs(found_est[cnt >= theta] - cnt[cnt >= theta]) / cnt[cnt >= theta]
+    return {"theta": theta, "n_true": n_true, "n_restored": int(found.size),
+            "fnr": fn / nh, "fpr": fp / nh, "ftr": (fn + fp) / nh,
+            "precision": tp / max(int(found.size), 1), "recall": tp / nh,
+            "est_rel_err_mean": float(rel.mean()) if rel.size else None,
+            "est_rel_err_p50": float(np.median(rel)) if rel.size else None,
+            "est_rel_err_p99": float(np.percentile(rel, 99)) if rel.size else None}
+
+
+def measure_ceilings(dev, stream, reps=5):
+    """The two ceilings the update is priced against, measured on this GPU with
+    the library's probes: a 1 GiB streaming copy (bytes read + written per
+    second), and random no-return 32-bit atomic ORs at precomputed addresses
+    into a 128 MiB buffer (one cube; fits the 256 MiB last-level cache) and a
+    512 MiB one (four cubes; does not)."""
+    import numpy as np
+    import torch
+
+    from paper_1901_06207_amd import cbaa
+
+    def timed(fn):
+        ms = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        return float(np.median(ms[1:]))
+
+    nb = 1 << 30
+    src = torch.ones(nb // 8, dtype=torch.int64, device=dev)
+    dst = torch.empty_like(src)
+    # the best of a few grid sizes, with cached and with nontemporal accesses
+    copies = {}
+    for blocks in (1024, 2048, 4096, 8192, 16384):
+        for flags in (0, cbaa.PROBE_NONTEMPORAL):
+            copies[(blocks, flags)] = timed(
+                lambda: cbaa.cbaa_probe_copy(dst, src, nb, blocks, flags, stream))
+    (best_blocks, best_flags), copy_ms = min(copies.items(), key=lambda kv: kv[1])
+
+    def torch_copy():
+        with torch.cuda.stream(stream):
+            dst.copy_(src)
+    torch_ms = timed(torch_copy)
+    del src, dst
+    n_ops = 1 << 26
+    addr = torch.empty(n_ops, dtype=torch.int32, device=dev)
+    out = {"hbm_copy_gbs": round(2 * nb / (copy_ms * 1e-3) / 1e9, 1),
+           "hbm_copy_bytes": 2 * nb,
+           "hbm_copy_shape": {"blocks": best_blocks, "threads": 256,
+                              "nontemporal": bool(best_flags)},
+           "hbm_copy_torch_gbs": round(2 * nb / (torch_ms * 1e-3) / 1e9, 1),
+           "atomic_ops": n_ops}
+    for mib in (128, 512):
+        words = (mib << 20) // 4
+        buf = torch.zeros(words, dtype=torch.int32, device=dev)
+        cbaa.cbaa_probe_addresses(addr, int(words).bit_length() - 1, 0x9E3779B9, stream)
+        a_ms = timed(lambda: cbaa.cbaa_probe_atomic_or(buf, addr, stream))
+        out[f"atomic_or_gops_{mib}MiB"] = round(n_ops / (a_ms * 1e-3) / 1e9, 2)
+        del buf
+    torch.cuda.synchronize(dev)
+    return out
 
 
 def calibrate_copy(dev, nbytes=1 << 30):
@@ -495,6 +621,117 @@ def bench_batched(cfg, dev, args):
     print(json.dumps(out), flush=True)
 
 
+# RA start bits per r for the sweep: |EP| = (10, 9, 10), (10, 9, 9), (9, 9, 9)
+# and |CP| = (2, 3, 2), (2, 3, 3), (3, 3, 3) with 12-bit column indices
+SWEEP_CL_BS = {3: [3, 13, 22], 4: [4, 14, 23], 5: [5, 14, 23]}
+
+
+def sweep_config(r, log2_g):
+    return dict(r=r, n_ra=3, n_va=1, log2_g=log2_g, cbn=[12, 12, 12, 12], cl_bs=SWEEP_CL_BS[r],
+                seed_mangle=0x243F6A88, seed_bv=0x85A308D3, seed_va=[0x13198A2E, 0x03707344])
+
+
+def bench_sweep(dev, args):
+    """Accuracy of the GPU's restored lists as the dimensions vary (Sec. 3.1-3.3
+    parameters; Sec. 5.2 rates): r in {3, 4, 5} (8-32 sketches), g in {2^11,
+    2^12, 2^13} bits per column, c = 2^12 columns per array, |RA| = 3, |VA| = 1,
+    under both threshold rules (THM2 and the printed Sec. 3.3 form), on
+    1M-packet windows (source-keyed) and 64Mi-packet core-edge windows (both
+    sides). Each row: array fill, the restore's counters and status, FNR, FPR,
+    FTR, precision, recall and the estimate's error against exact counts."""
+    import numpy as np
+    import torch
+
+    import tracegen
+    from paper_1901_06207_amd import cbaa
+
+    windows = []
+    for part in args.sweep_windows.split(";"):
+        kind, seeds = part.split(":")
+        windows += [(kind, int(x)) for x in seeds.split(",")]
+    rows = []
+    t_all = time.time()
+    for kind, seed in windows:
+        t0 = time.time()
+        tr = (tracegen.window_small(seed) if kind == "small"
+              else tracegen.window_core_edge(seed, scale=args.scale))
+        sides = (0,) if kind == "small" else (0, 1)
+        truth = {}
+        for side in sides:
+            h, c = tracegen.construction_truth(tr, side)
+            o = np.argsort(h, kind="stable")
+            truth[side] = (h[o], c[o])
+            del h, c, o
+        d_pairs = cbaa.pairs_to_device(tr.pairs, dev)
+        log(f"sweep window {kind}:{seed} ({tr.n} packets) ready in {time.time() - t0:.1f}s")
+        for r in (3, 4, 5):
+            for log2_g in (11, 12, 13):
+                p = sweep_config(r, log2_g)
+                cubes = [cbaa.new_cube(p, dev) for _ in sides]
+                nb = cbaa.cbaa_update_scratch_bytes(p, tr.n, len(sides))
+                scratch = cbaa.scratch_tensor(nb, dev) if nb else None
+                torch.cuda.synchronize(dev)
+                tu = time.perf_counter()
+                if len(sides) == 2:
+                    cbaa.cbaa_update2(p, cubes[0], cubes[1], d_pairs, scratch)
+                else:
+                    cbaa.cbaa_update(p, cubes[0], d_pairs, cbaa.SIDE_SRC, scratch)
+                torch.cuda.synchronize(dev)
+                upd_ms = (time.perf_counter() - tu) * 1e3
+                del scratch
+                g = 1 << log2_g
+                A, S, W = 4, 1 << r, 4 * 4096
+                for side, cube in zip(sides, cubes):
+                    zs = cbaa.scratch_tensor(cbaa.cbaa_restore_scratch_bytes(p, 0), dev)
+                    zeros = torch.empty(S * W, dtype=torch.int16, device=dev)
+                    ones = torch.empty(S * A, dtype=torch.int32, device=dev)
+                    cbaa.cbaa_column_zeros(p, cube, zeros, ones)
+                    fill = ones.cpu().numpy().astype(np.float64).reshape(S, A) / (4096.0 * g)
+                    del zs, zeros
+                    for rule, rname in ((cbaa.THR_THM2, "THM2"), (cbaa.THR_PAPER, "PAPER")):
+                        tr0 = time.perf_counter()
+                        lst, st = cbaa.restore(p, cube, args.theta, rule, capacity=1 << 14,
+                                               max_checks=1 << 26)
+                        rest_ms = (time.perf_counter() - tr0) * 1e3
+                        acc = detection_accuracy(lst["ip"], lst["est"], *truth[side], args.theta,
+                                                 hosts_sorted=True)
+                        row = {"window": f"{kind}:{seed}", "packets": int(tr.n),
+                               "side": "source" if side == 0 else "destination",
+                               "r": r, "g": g, "rule": rname,
+                               "fill_mean": round(float(fill.mean()), 5),
+                               "fill_max": round(float(fill.max()), 5),
+                               "eps_max": float(np.prod(fill, axis=1).max()),
+                               "update_ms": round(upd_ms, 2),
+                               "path": "partitioned" if nb else "direct",
+                               "restore_ms": round(rest_ms, 2),
+                               "hot_columns": st["hot_columns"], "tuple_space": st["tuple_space"],
+                               "status": st["status"]}
+                        row.update({k: (round(v, 6) if isinstance(v, float) else v)
+                                    for k, v in acc.items()})
+                        rows.append(row)
+                        log(f"  r={r} g={g} {row['side']} {rname}: fill {row['fill_mean']:.4f} "
+                            f"FNR {row['fnr']:.4f} FPR {row['fpr']:.4f} hosts {row['n_restored']} "
+                            f"status {row['status']} ({rest_ms:.1f} ms)")
+                del cubes
+        del d_pairs, tr, truth
+        torch.cuda.empty_cache()
+    # summary per (r, g, rule): mean FNR/FPR/FTR over windows and sides
+    summary = []
+    keys = sorted({(x["r"], x["g"], x["rule"]) for x in rows})
+    for r, g, rule in keys:
+        sel = [x for x in rows if (x["r"], x["g"], x["rule"]) == (r, g, rule)]
+        summary.append({"r": r, "g": g, "rule": rule, "cases": len(sel),
+                        "fnr": round(float(np.mean([x["fnr"] for x in sel])), 6),
+                        "fpr": round(float(np.mean([x["fpr"] for x in sel])), 6),
+                        "ftr": round(float(np.mean([x["ftr"] for x in sel])), 6),
+                        "fill_mean": round(float(np.mean([x["fill_mean"] for x in sel])), 5),
+                        "incomplete": sum(1 for x in sel if x["status"])})
+    out = {"metric": METRIC, "workload": "sweep", "theta": args.theta,
+           "windows": [f"{k}:{s}" for k, s in windows], "wall_s": round(time.time() - t_all, 1),
+           "summary": summary, "rows": rows}
+    print(json.dumps(out), flush=True)
+
+
 def bench_serving(cfg, dev, args):
     """16 edge routers send Poisson-arriving chunks of 64k-4M pairs; a 60 s
     simulated window is replayed in compressed time; continuous batching
@@ -581,21 +818,71 @@ def bench_learned(cfg, trace, g_src, local, dev, args):
                      for b in rep["bins"]]}
 
 
+def host_info():
+    """CPU model and core counts of the machine the oracle is timed on."""
+    import subprocess
+    model = None
+    try:
+        out = subprocess.run(["lscpu"], capture_output=True, text=True, timeout=10).stdout
+        for line in out.splitlines():
+            if line.startswith("Model name:"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except (OSError, subprocess.SubprocessError):
+        pass
+    if model is None and os.path.exists("/proc/cpuinfo"):
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    return {"nproc": os.cpu_count(), "usable_cores": len(os.sched_getaffinity(0)),
+            "model": model, "omp_num_threads_env": os.environ.get("OMP_NUM_THREADS")}
+
+
 def cpu_baseline(pairs, sample, theta):
     """The oracle's step (both cubes' update, both restores) on the first
-    `sample` packets of the window (all by default), single-threaded."""
+    `sample` packets of the window (all by default): single-threaded (the
+    reported value), and again with the update split over the host's cores
+    (OpenMP, atomic ORs); the exact per-host counts (sort-unique) are timed
+    beside it both ways."""
     import oracle as O
     p = O.default_params()
     s = pairs[:sample] if sample else pairs
     t0 = time.perf_counter()
     a = O.cube_of(p, s, O.SIDE_SRC)
     b = O.cube_of(p, s, O.SIDE_DST)
+    t1 = time.perf_counter()
     O.restore(p, a, theta)
     O.restore(p, b, theta)
     dt = time.perf_counter() - t0
+    restore_s = time.perf_counter() - t1
+    t0 = time.perf_counter()
+    O.exact_counts(s, O.SIDE_SRC)
+    exact_1 = time.perf_counter() - t0
+    threads = O.omp_threads()
+    a2, b2 = O.new_cube(p), O.new_cube(p)
+    t0 = time.perf_counter()
+    O.update_omp(p, a2, s, O.SIDE_SRC)
+    O.update_omp(p, b2, s, O.SIDE_DST)
+    upd_omp = time.perf_counter() - t0
+    O.restore(p, a2, theta)
+    O.restore(p, b2, theta)
+    dt_omp = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    O.exact_counts_omp(s, O.SIDE_SRC)
+    exact_omp = time.perf_counter() - t0
     return {"value": round(len(s) / dt / 1e9, 6), "unit": "Gpkt/s", "cores": 1, "kind": "oracle",
             "sample": (f"{len(s)} packets of the window: oracle update of both cubes "
-                       f"plus both restores, {dt:.1f}s single-threaded")}
+                       f"plus both restores, {dt:.1f}s single-threaded"),
+            "update_s": round(dt - restore_s, 3), "restore_s_both": round(restore_s, 3),
+            "exact_counts_s_one_side": round(exact_1, 3),
+            "host": host_info(),
+            "openmp": {"value": round(len(s) / dt_omp / 1e9, 6), "unit": "Gpkt/s",
+                       "cores": threads, "update_s": round(upd_omp, 3),
+                       "restore_s_both": round(dt_omp - upd_omp, 3),
+                       "exact_counts_s_one_side": round(exact_omp, 3),
+                       "note": "update over all threads with atomic ORs; the restore is the "
+                               "oracle's single-threaded one"}}
 
 
 if __name__ == "__main__":

@@ -85,6 +85,9 @@ def _load():
         "ref_estimate": (None, [cfgp, u64p, u32p, C.c_uint64, f64p, u16p, u8p]),
         "ref_host_layer_zeros": (None, [cfgp, u64p, u32p, C.c_uint64, u16p]),
         "ref_exact_counts": (C.c_uint64, [u32p, C.c_uint64, C.c_int, u32p, u32p]),
+        "ref_exact_counts_omp": (C.c_uint64, [u32p, C.c_uint64, C.c_int, u32p, u32p]),
+        "ref_update_omp": (None, [cfgp, u64p, u32p, C.c_uint64, C.c_int]),
+        "ref_omp_threads": (C.c_int, []),
         "ref_row_ones": (None, [cfgp, u64p, u32p]),
         "ref_row_shared": (None, [cfgp, u32p, f64p]),
         "ref_check_mangle_bijection": (C.c_uint64, [cfgp]),
@@ -175,6 +178,17 @@ def cube_of(p: dict, pairs: np.ndarray, side: int) -> np.ndarray:
     cube = new_cube(p)
     update(p, cube, pairs, side)
     return cube
+
+
+def update_omp(p: dict, cube: np.ndarray, pairs: np.ndarray, side: int) -> None:
+    """update() split over all host cores with atomic ORs (a timing leg)."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.uint32)
+    assert cube.dtype == np.uint64 and cube.size == cube_words(p)
+    _load().ref_update_omp(C.byref(_cfg(p)), _ptr(cube), _ptr(pairs), pairs.shape[0], side)
+
+
+def omp_threads() -> int:
+    return int(_load().ref_omp_threads())
 
 
 def merge_or(p: dict, cubes: list[np.ndarray]) -> np.ndarray:
@@ -271,6 +285,16 @@ def exact_counts(pairs: np.ndarray, side: int) -> tuple[np.ndarray, np.ndarray]:
     hosts = np.zeros(max(n, 1), np.uint32)
     counts = np.zeros(max(n, 1), np.uint32)
     nh = _load().ref_exact_counts(_ptr(pairs), n, side, _ptr(hosts), _ptr(counts))
+    return hosts[:nh].copy(), counts[:nh].copy()
+
+
+def exact_counts_omp(pairs: np.ndarray, side: int) -> tuple[np.ndarray, np.ndarray]:
+    """exact_counts() over all host cores (bucketed by the host's top byte)."""
+    pairs = np.ascontiguousarray(pairs, dtype=np.uint32)
+    n = pairs.shape[0]
+    hosts = np.zeros(max(n, 1), np.uint32)
+    counts = np.zeros(max(n, 1), np.uint32)
+    nh = _load().ref_exact_counts_omp(_ptr(pairs), n, side, _ptr(hosts), _ptr(counts))
     return hosts[:nh].copy(), counts[:nh].copy()
 
 

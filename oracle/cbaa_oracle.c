@@ -54,6 +54,7 @@
  * multiply-add changes a rounding.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -316,6 +317,33 @@ void ref_merge_or(const ref_config* c, uint64_t* dst, const uint64_t* const* src
     dst[w] = acc;
   }
 }
+
+/* Timing leg over all host cores (used only by the benchmark's CPU baseline
+ * and the test that checks it against ref_update): the pairs are divided
+ * among OpenMP threads and every bit is set with an atomic OR. The update
+ * only ever sets bits (Sec. 3.2), so the cube is the same set union as
+ * ref_update's whatever the interleaving. */
+void ref_update_omp(const ref_config* c, uint64_t* cube, const uint32_t* pairs, uint64_t n,
+                    int side) {
+  layout l = layout_of(c);
+  const uint32_t A = n_arrays(c);
+#pragma omp parallel for schedule(static, 65536)
+  for (int64_t k = 0; k < (int64_t)n; ++k) {
+    uint32_t src = pairs[2 * k], dst = pairs[2 * k + 1];
+    uint32_t iip = side == REF_SIDE_SRC ? src : dst;
+    uint32_t oip = side == REF_SIDE_SRC ? dst : src;
+    uint32_t cols[REF_MAX_ARRAYS];
+    uint32_t cs;
+    uint32_t bv = ref_hash_bv(c, oip);
+    ref_host_columns(c, iip, &cs, cols);
+    for (uint32_t a = 0; a < A; ++a)
+      __atomic_fetch_or(&cube[word_index(&l, cs, a, cols[a], bv)], 1ull << (bv & 63u),
+                        __ATOMIC_RELAXED);
+  }
+}
+
+/* Threads an OpenMP region of the oracle runs with. */
+int ref_omp_threads(void) { return omp_get_max_threads(); }
 
 /* ------------------------------------------------------------------ */
 /* Column statistics and thresholds (Alg. 2, Thm. 1, Thm. 2)            */
@@ -689,6 +717,83 @@ uint64_t ref_exact_counts(const uint32_t* pairs, uint64_t n, int side, uint32_t*
   }
   free(keys);
   return nh;
+}
+
+/* ref_exact_counts over all host cores (benchmark timing leg; tested
+ * against ref_exact_counts): the (host, peer) keys are bucketed by the
+ * host's top 8 bits, each bucket is sorted and counted by one thread, and the
+ * buckets are concatenated in order, so the output is the same ascending
+ * list. */
+uint64_t ref_exact_counts_omp(const uint32_t* pairs, uint64_t n, int side, uint32_t* hosts_out,
+                              uint32_t* counts_out) {
+  enum { NB = 256 };
+  if (n == 0) return 0;
+  const int T = omp_get_max_threads();
+  uint64_t* keys = (uint64_t*)malloc(n * sizeof(uint64_t));
+  uint64_t* hist = (uint64_t*)calloc((size_t)T * NB, sizeof(uint64_t));
+  uint64_t start[NB + 1];
+  uint64_t nh_b[NB];
+#pragma omp parallel num_threads(T)
+  {
+    const int t = omp_get_thread_num();
+    const uint64_t lo = n * (uint64_t)t / (uint64_t)T, hi = n * (uint64_t)(t + 1) / (uint64_t)T;
+    uint64_t* h = hist + (size_t)t * NB;
+    for (uint64_t k = lo; k < hi; ++k) {
+      uint32_t host = side == REF_SIDE_SRC ? pairs[2 * k] : pairs[2 * k + 1];
+      h[host >> 24]++;
+    }
+#pragma omp barrier
+#pragma omp single
+    {
+      uint64_t acc = 0;
+      for (int b = 0; b < NB; ++b) {
+        start[b] = acc;
+        for (int u = 0; u < T; ++u) {
+          uint64_t v = hist[(size_t)u * NB + b];
+          hist[(size_t)u * NB + b] = acc;
+          acc += v;
+        }
+      }
+      start[NB] = acc;
+    }
+    for (uint64_t k = lo; k < hi; ++k) {
+      uint32_t src = pairs[2 * k], dst = pairs[2 * k + 1];
+      uint32_t host = side == REF_SIDE_SRC ? src : dst;
+      uint32_t peer = side == REF_SIDE_SRC ? dst : src;
+      keys[h[host >> 24]++] = ((uint64_t)host << 32) | peer;
+    }
+#pragma omp barrier
+#pragma omp for schedule(dynamic, 1)
+    for (int b = 0; b < NB; ++b) {
+      uint64_t* kb = keys + start[b];
+      const uint64_t m = start[b + 1] - start[b];
+      qsort(kb, m, sizeof(uint64_t), cmp_u64);
+      /* distinct hosts of the bucket with their distinct peers, written in
+       * place at the front of the bucket's key range */
+      uint64_t nh = 0, prev = 0;
+      for (uint64_t k = 0; k < m; ++k) {
+        const uint64_t key = kb[k];   /* read before slot nh <= k is rewritten */
+        if (k > 0 && key == prev) continue;
+        prev = key;
+        uint32_t host = (uint32_t)(key >> 32);
+        if (nh > 0 && (uint32_t)(kb[nh - 1] >> 32) == host) {
+          kb[nh - 1]++;
+        } else {
+          kb[nh++] = ((uint64_t)host << 32) | 1u;
+        }
+      }
+      nh_b[b] = nh;
+    }
+  }
+  uint64_t out = 0;
+  for (int b = 0; b < NB; ++b)
+    for (uint64_t k = 0; k < nh_b[b]; ++k, ++out) {
+      hosts_out[out] = (uint32_t)(keys[start[b] + k] >> 32);
+      counts_out[out] = (uint32_t)keys[start[b] + k];
+    }
+  free(hist);
+  free(keys);
+  return out;
 }
 
 /* ------------------------------------------------------------------ */

@@ -170,6 +170,9 @@ def lib():
         "cbaa_mlp_loss_grad": (i32, [C.c_uint32, vp, vp, vp, vp, u64, vp, vp, vp]),
         "cbaa_mlp_adam": (i32, [C.c_uint32, vp, vp, vp, vp, vp, C.c_uint32, C.c_float,
                                 C.c_float, C.c_float, C.c_float, vp]),
+        "cbaa_probe_copy": (i32, [vp, vp, u64, C.c_uint32, C.c_uint32, vp]),
+        "cbaa_probe_addresses": (i32, [vp, u64, C.c_uint32, C.c_uint32, vp]),
+        "cbaa_probe_atomic_or": (i32, [vp, u64, vp, u64, vp]),
         "cbaa_strerror": (C.c_char_p, [i32]),
         "cbaa_last_error": (C.c_char_p, []),
     }
@@ -412,6 +415,31 @@ def cbaa_estimate(cfg, cube: torch.Tensor, hosts: torch.Tensor, est: torch.Tenso
                                _dev_ptr(layer_zeros, "layer_zeros", 2 * n * A) if n else None,
                                _dev_ptr(scratch, "scratch"), sb, _stream(stream)),
            "cbaa_estimate")
+
+
+# ---- measurement probes (include/cbaa_probe.h) ---------------------------------
+
+PROBE_NONTEMPORAL = 1
+
+
+def cbaa_probe_copy(dst: torch.Tensor, src: torch.Tensor, nbytes: int, blocks: int = 0,
+                    flags: int = 0, stream=None) -> None:
+    _check(lib().cbaa_probe_copy(_dev_ptr(dst, "dst", nbytes), _dev_ptr(src, "src", nbytes),
+                                 nbytes, blocks, flags, _stream(stream)), "cbaa_probe_copy")
+
+
+def cbaa_probe_addresses(addr: torch.Tensor, log2_words: int, seed: int, stream=None) -> None:
+    n = int(addr.numel())
+    _check(lib().cbaa_probe_addresses(_dev_ptr(addr, "addr", 4 * n), n, log2_words, seed,
+                                      _stream(stream)), "cbaa_probe_addresses")
+
+
+def cbaa_probe_atomic_or(buf: torch.Tensor, addr: torch.Tensor, stream=None) -> None:
+    words = buf.numel() * buf.element_size() // 4
+    n = int(addr.numel())
+    _check(lib().cbaa_probe_atomic_or(_dev_ptr(buf, "buf", 4 * words), words,
+                                      _dev_ptr(addr, "addr", 4 * n), n, _stream(stream)),
+           "cbaa_probe_atomic_or")
 
 
 # ---- learned estimator (include/cbaa_mlp.h) ------------------------------------

@@ -620,3 +620,28 @@ def test_column_zeros_by_unpacking_every_bit(name):
     want_ones = np.stack([col_ones[:, aoff[a]:aoff[a] + ncol[a]].sum(axis=1) for a in range(A)], 1)
     assert np.array_equal(ones.reshape(S, A), want_ones)
     assert col_ones.max() > 0 and (g - col_ones).min() < g
+
+
+def test_openmp_timing_legs_equal_the_plain_oracle():
+    """The benchmark's multi-core CPU leg computes what the plain oracle does:
+    the atomic-OR update gives the same cube bytes, the bucketed sort-unique
+    the same (host, count) list, on a window with duplicates and both sides."""
+    import tracegen
+    p = default_params()
+    t = tracegen.make_window(400_000, 40_000, 12, 1_000, 8_000, dup_frac=0.1, fan_in_frac=0.5,
+                             seed=31)
+    for side in (O.SIDE_SRC, O.SIDE_DST):
+        want = O.cube_of(p, t.pairs, side)
+        got = O.new_cube(p)
+        O.update_omp(p, got, t.pairs, side)
+        assert np.array_equal(got, want)
+        h0, c0 = O.exact_counts(t.pairs, side)
+        h1, c1 = O.exact_counts_omp(t.pairs, side)
+        assert np.array_equal(h0, h1) and np.array_equal(c0, c1)
+    # hosts that share a top byte, and a run of one host's repeated pairs
+    pairs = np.array([[0x01000005, 9], [0x01000005, 9], [0x01000004, 9], [0x01FFFFFF, 1],
+                      [0x01000004, 8], [0xFF000000, 2]], dtype=np.uint32)
+    h, c = O.exact_counts_omp(pairs, O.SIDE_SRC)
+    assert h.tolist() == [0x01000004, 0x01000005, 0x01FFFFFF, 0xFF000000]
+    assert c.tolist() == [2, 1, 1, 1]
+    assert O.omp_threads() >= 1

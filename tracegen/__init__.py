@@ -173,14 +173,12 @@ def construction_truth(t: Trace, side: int) -> tuple[np.ndarray, np.ndarray]:
     peers of every other flow (one peer each)."""
     n_bg = t.bg_ips.size
     deg = np.concatenate([t.bg_deg, t.planted_deg])
-    ends = np.cumsum(deg)
-    starts = ends - deg
     fan_in = np.concatenate([np.zeros(n_bg, bool), t.planted_side.astype(bool)])
 
     def peers_of(mask):
-        idx = np.concatenate([np.arange(a, b, dtype=np.uint64)
-                              for a, b in zip(starts[mask], ends[mask])]) \
-            if mask.any() else np.zeros(0, np.uint64)
+        # flow k belongs to the host whose [start, end) range holds it; the
+        # flows of the selected hosts, in host order
+        idx = np.nonzero(np.repeat(mask, deg))[0].astype(np.uint64)
         return bijection32(np.uint64(1 << 31) + idx, t.key)
 
     if side == 0:
