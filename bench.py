@@ -84,6 +84,9 @@ def parse():
     ap.add_argument("--sweep-windows", default="small:1,2,3;core-edge:11,12,13",
                     help="windows of the sweep: kind:seeds;kind:seeds")
     ap.add_argument("--streams", type=int, default=32)
+    ap.add_argument("--update-streams", choices=["one", "per-router"], default="one",
+                    help="one: all routers' packets in one batched update call; per-router: "
+                         "each router's batch on its own stream, overlapping on the device")
     ap.add_argument("--store-merged", action="store_true",
                     help="the window end also stores each side's merged (global) cube")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -135,7 +138,16 @@ def main():
         tuning = tune_info["best"]
         log(f"autotuned: {tune_info['best']} {tune_info['best_ms']:.3f} ms "
             f"(default {tune_info['default_ms']:.3f} ms)")
-    scratch_u = cbaa.scratch_tensor(cbaa.cbaa_update_batch_scratch_bytes(cfg, table, tuning), dev)
+    per_router = args.update_streams == "per-router" and len(parts) > 1
+    if per_router:
+        # each local server updates its own cubes on its own stream: the
+        # routers' launch sequences overlap on the device
+        tables = [[t] for t in table]
+        scratch_us = [cbaa.scratch_tensor(cbaa.cbaa_update_batch_scratch_bytes(cfg, t, tuning), dev)
+                      for t in tables]
+        ustreams = [torch.cuda.Stream(device=dev) for _ in tables]
+    else:
+        scratch_u = cbaa.scratch_tensor(cbaa.cbaa_update_batch_scratch_bytes(cfg, table, tuning), dev)
 
     g_src = cbaa.new_cube(cfg, dev, init=False)
     g_dst = cbaa.new_cube(cfg, dev, init=False)
@@ -163,7 +175,20 @@ def main():
     def step(stream, timed=False):
         if timed:
             mark("update", stream)
-        cbaa.cbaa_update_batch(cfg, table, scratch_u, tuning, stream)
+        if per_router:
+            fork = torch.cuda.Event()
+            fork.record(stream)
+            joins = []
+            for t, sc, us in zip(tables, scratch_us, ustreams):
+                us.wait_event(fork)
+                cbaa.cbaa_update_batch(cfg, t, sc, tuning, us)
+                e = torch.cuda.Event()
+                e.record(us)
+                joins.append(e)
+            for e in joins:
+                stream.wait_event(e)
+        else:
+            cbaa.cbaa_update_batch(cfg, table, scratch_u, tuning, stream)
         if timed:
             mark("window_end", stream)
         # global server: OR-merge the routers' cubes and restore, per side.
@@ -272,7 +297,9 @@ def main():
                 # kernels run to the memory system on the bytes they do move
                 "traffic_frac": (round(traffic / (upd_ms.mean() * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)
                                  if traffic else None),
-                "kernel": "cbaa_update_batch (histogram, scan, scatter, apply)",
+                "kernel": ("cbaa_update_batch (histogram, scan, scatter, apply), "
+                           + ("one call per router on its own stream, overlapping; timed from "
+                              "the fork to the join" if per_router else "one call for all routers")),
                 "per_launch": {"packets": int(trace.n), "alg_bytes": int(upd_alg_bytes),
                                "avg_ms": round(float(upd_ms.mean()), 4)}}
 
@@ -361,6 +388,7 @@ def main():
                          "r=4 |RA|=3 |VA|=1 g=c=4096"),
             "packets": trace.n, "routers": args.routers, "seed": args.seed,
             "launch": "eager" if graph is None else "hip-graph",
+            "update_streams": args.update_streams if len(parts) > 1 else "one",
             "tuning": tuning or "default",
             "merged_cube": ("stored" if args.store_merged else
                             "not stored: the restore reads columns as the OR of the router cubes"),
@@ -740,7 +768,7 @@ def bench_serving(cfg, dev, args):
     import torch
 
     import tracegen
-    from paper_1901_06207_amd import serve
+    from paper_1901_06207_amd import cbaa, serve
 
     n_routers, window_s, lo, hi = 16, 60.0, 65536, 4 << 20
     rate = 0.25                 # chunks per router per simulated second (~240 per window)
@@ -755,7 +783,11 @@ def bench_serving(cfg, dev, args):
         q = np.ascontiguousarray(pairs[pos:pos + size]).view(np.int32)
         pos += size
         chunks.append(torch.from_numpy(q).pin_memory())
-    srv = serve.Server(cfg, n_routers, both_sides=True, staging_bytes=1 << 30, device=dev)
+    # cubes for 12 of the 16 routers: the least recently used idle router is
+    # retired into the global cubes when another one needs room
+    per_router = 2 * cbaa.cbaa_cube_bytes(cfg)
+    srv = serve.Server(cfg, n_routers, both_sides=True, staging_bytes=1 << 30,
+                       cube_budget_bytes=12 * per_router, device=dev)
     # warm the kernels once on a few chunks
     serve.run_window(srv, events[:8], chunks[:8], time_scale=0.0)
     # saturation: every chunk arrives at once
@@ -772,48 +804,101 @@ def bench_serving(cfg, dev, args):
             "saturation_gpkt_s": round(sat["gpkt_s"], 3),
             "offered_gpkt_s": offered, "gpkt_s": round(res["gpkt_s"], 3),
             "p50_ms": round(res["p50_ms"], 3), "p99_ms": round(res["p99_ms"], 3),
+            "result_p50_ms": round(res["result_p50_ms"], 3),
+            "result_p99_ms": round(res["result_p99_ms"], 3),
+            "cube_budget_routers": 12, "cube_peak_mib": round(res["cube_peak_bytes"] / 2 ** 20, 1),
+            "retirements": res["retirements"],
             "batches": res["batches"],
             "staging_peak_mib": round(res["staging_peak_bytes"] / 2 ** 20, 1),
             "window_restore_ms": round(res["restore_ms"], 3),
-            "note": "chunks are copied host-to-device inside the measured latency"}
+            "note": ("p50/p99: a chunk's arrival to its update done on the device (its "
+                     "host-to-device copy included); result_p50/p99: arrival to the restored "
+                     "lists of its window on the host (the compressed window replay included)")}
 
 
 def bench_learned(cfg, trace, g_src, local, dev, args):
-    """The learned estimator trained on half of the window's source hosts
-    (labels: the generator's construction counts) and compared with the
-    paper's linear count on the other half at equal false-negative rate."""
+    """The learned estimator trained on other windows and evaluated on this
+    one: three core-edge-shaped training windows of other seeds (32Mi packets
+    each, source-keyed cubes), at least 4M host rows drawn stratified by
+    cardinality with exact counts; evaluation on up to 2M hosts of the
+    benchmark's own window (its merged source-keyed cube), against the paper's
+    linear count and the row-aware count at equal false-negative rate. Also
+    the network's inference and training throughput on the device."""
     import numpy as np
     import torch
 
     import tracegen
     from paper_1901_06207_amd import cbaa, learned
 
-    # the global source-keyed cube of the last step holds the whole window
-    hosts, counts = tracegen.construction_truth(trace, 0)
     rng = np.random.default_rng(args.seed)
-    perm = rng.permutation(hosts.size)
-    half = perm.size // 2
-    tr_pool, te = perm[:half], perm[half:]
-    tr = tr_pool[learned.stratified_rows(counts[tr_pool], 100_000, rng)]
-    te = rng.choice(te, min(te.size, 2_000_000), replace=False)
     t0 = time.perf_counter()
-    x_tr = learned.features(cfg, g_src, hosts[tr])
+    xs, ts = [], []
+    train_seeds = [args.seed + 101, args.seed + 102, args.seed + 103]
+    for s in train_seeds:
+        tw = tracegen.window_core_edge(s, scale=0.5 * args.scale)
+        cube = cbaa.new_cube(cfg, dev)
+        nb = cbaa.cbaa_update_scratch_bytes(cfg, tw.n, 1)
+        sc = cbaa.scratch_tensor(nb, dev)
+        cbaa.cbaa_update(cfg, cube, cbaa.pairs_to_device(tw.pairs, dev), cbaa.SIDE_SRC, sc)
+        del sc
+        hosts, counts = tracegen.construction_truth(tw, 0)
+        idx = learned.stratified_rows(counts, 700_000, rng)
+        xs.append(learned.features(cfg, cube, hosts[idx]))
+        ts.append(torch.from_numpy(np.log1p(counts[idx]).astype(np.float32)).to(dev))
+        del cube, tw, hosts, counts
+    x_tr = torch.cat(xs).contiguous()
+    t_tr = torch.cat(ts).contiguous()
+    del xs, ts
+    prep_s = time.perf_counter() - t0
     model = learned.Model.new(x_tr.shape[1], seed=1)
-    tl = learned.train(model, x_tr, torch.from_numpy(np.log1p(counts[tr]).astype(np.float32)).to(dev),
-                       epochs=20, batch=16384)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    tl = learned.train(model, x_tr, t_tr, epochs=6, batch=65536)
     torch.cuda.synchronize(dev)
     train_s = time.perf_counter() - t0
+    # evaluation on the benchmark's window
+    hosts, counts = tracegen.construction_truth(trace, 0)
+    te = rng.choice(hosts.size, min(hosts.size, 2_000_000), replace=False)
     x_te = learned.features(cfg, g_src, hosts[te])
     est_ml = learned.predict(model, x_te).cpu().numpy()
     est_lc = learned.linear_count(cfg, g_src, hosts[te])
     est_row = learned.row_aware_count(x_te).cpu().numpy()
     rep = learned.compare(est_lc, est_ml, counts[te], args.theta, est_row=est_row)
-    return {"train_rows": int(tr.size), "test_rows": int(te.size), "epochs": tl.epochs,
-            "features": int(x_tr.shape[1]),
-            "train_s": round(train_s, 2), "final_loss": round(tl.final_loss, 5),
+    # throughput: forward over the evaluation rows, one gradient over a batch
+    y = torch.empty(x_te.shape[0], dtype=torch.float32, device=dev)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        e0.record()
+        cbaa.cbaa_mlp_forward(model.n_features, model.master, model.wbf, x_te, y)
+        e1.record()
+        e1.synchronize()
+    fwd_ms = e0.elapsed_time(e1)
+    grad = torch.empty(model.master.numel(), dtype=torch.float32, device=dev)
+    loss = torch.empty(1, dtype=torch.float32, device=dev)
+    nb_ = min(x_tr.shape[0], 1 << 20)
+    for _ in range(2):
+        e0.record()
+        cbaa.cbaa_mlp_loss_grad(model.n_features, model.master, model.wbf, x_tr[:nb_],
+                                t_tr[:nb_], grad, loss)
+        e1.record()
+        e1.synchronize()
+    grad_ms = e0.elapsed_time(e1)
+    mlp_fpr, row_fpr = rep["mlp"]["fpr"], rep["row"]["fpr"]
+    return {"train_windows": [f"core-edge seed {s}, 32Mi packets" for s in train_seeds],
+            "train_rows": int(x_tr.shape[0]), "test_rows": int(te.size),
+            "test_window": f"the benchmark's window (seed {args.seed})",
+            "epochs": tl.epochs, "features": int(x_tr.shape[1]),
+            "prep_s": round(prep_s, 2), "train_s": round(train_s, 2),
+            "final_loss": round(tl.final_loss, 5),
+            "forward_samples_per_s": round(x_te.shape[0] / (fwd_ms * 1e-3), 1),
+            "grad_samples_per_s": round(nb_ / (grad_ms * 1e-3), 1),
             "lc": {k: round(v, 5) for k, v in rep["lc"].items()},
             "row": {k: round(v, 5) for k, v in rep["row"].items()},
             "mlp": {k: (round(v, 5) if isinstance(v, float) else v) for k, v in rep["mlp"].items()},
+            "mlp_vs_row_at_equal_fnr": (
+                "the network is better than the row-aware count" if mlp_fpr < row_fpr else
+                "the network is NOT better than the row-aware count" if mlp_fpr > row_fpr else
+                "the network ties the row-aware count") + f" (FPR {mlp_fpr:.4f} vs {row_fpr:.4f})",
             "bins": [{k: (round(v, 4) if isinstance(v, float) else v) for k, v in b.items()}
                      for b in rep["bins"]]}
 

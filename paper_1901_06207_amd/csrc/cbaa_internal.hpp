@@ -47,12 +47,14 @@ __device__ inline bool header_ok(const uint64_t* h, const Dims& d) {
          h[3] == (uint64_t)CBAA_ABI_VERSION;   // state VALID in the high half
 }
 
-// Writes the four defined header words (state VALID or MIXED).
+// Writes a whole header: the four defined words (state VALID or MIXED) and
+// the reserved words, which are zero.
 __device__ inline void header_set(uint64_t* h, const Dims& d, uint32_t state) {
   h[0] = CBAA_CUBE_MAGIC;
   h[1] = d.hash;
   h[2] = d.words * 8u;
   h[3] = ((uint64_t)state << 32) | CBAA_ABI_VERSION;
+  for (uint64_t w = 4; w < kHeaderWords; ++w) h[w] = 0;
 }
 
 // A cube about to receive more bits keeps a valid header only if it has one.

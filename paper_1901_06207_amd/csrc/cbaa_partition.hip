@@ -14,8 +14,9 @@
 //                  bin's records are contiguous) and of apply segments; the
 //                  bins' write cursors start at their bases
 //   3. items       apply items prefixed over streams
-//   4. scatter     persistent blocks (one per CU) take scatter chunks, kept in
-//                  registers, from a shared counter; per
+//   4. scatter     persistent blocks (one per CU, 768 threads) take scatter
+//                  chunks (20 pairs per thread), kept in registers, from a
+//                  shared counter; per
 //                  cube, rank the chunk's records inside their bins in LDS,
 //                  reserve each bin's run with one atomic add on its cursor,
 //                  stage the records bin-sorted and write every run
@@ -42,8 +43,12 @@ constexpr uint32_t kMaxBins = 2048;
 constexpr int kUnroll = 8;                // independent loads in flight per thread
 constexpr int kApplyUnroll = 16;
 constexpr uint32_t kMaxTileWords = 16384; // 128 KiB LDS tile
-constexpr int kScatterPer = 12;           // pairs per thread in a scatter chunk
-constexpr uint32_t kScatterChunk = kScatterPer * kBlock;
+// Scatter blocks of 768 threads (12 waves) have 168 registers per lane: a
+// chunk of 20 pairs per thread stays in registers with no spill, and its
+// 8-byte records fill 120 KiB of LDS.
+constexpr int kScatterThreads = 768;
+constexpr int kScatterPer = 20;           // pairs per thread in a scatter chunk
+constexpr uint32_t kScatterChunk = kScatterPer * kScatterThreads;
 constexpr uint32_t kScatterBlocks = 256;  // persistent scatter grid (one per CU)
 constexpr uint32_t kDefaultChunk = 65536;
 constexpr uint32_t kDefaultSeg = 65536;
@@ -217,7 +222,8 @@ __global__ __launch_bounds__(kBlock) void k_histogram(Dims d, Batch b, uint32_t*
   }
 }
 
-// Exclusive scan of per-thread values over the block (kBlock threads).
+// Exclusive scan of per-thread values over a block of T threads.
+template <int T = kBlock>
 __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_waves, uint32_t& total) {
   const uint32_t lane = __lane_id();
   const uint32_t wid = threadIdx.x / kWave;
@@ -231,7 +237,7 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_waves,
   if (lane == kWave - 1) lds_waves[wid] = incl;
   __syncthreads();
   uint32_t before = 0, tot = 0;
-  for (uint32_t w = 0; w < kBlock / kWave; ++w) {
+  for (uint32_t w = 0; w < T / kWave; ++w) {
     if (w < wid) before += lds_waves[w];
     tot += lds_waves[w];
   }
@@ -300,7 +306,7 @@ __device__ inline uint32_t pack_rank(uint32_t rk, int u, uint32_t rank) {
 __device__ inline uint32_t unpack_rank(uint32_t rk, int u) { return (rk >> (16 * (u & 1))) & 0xFFFFu; }
 
 template <bool TWO>
-__global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* cursor,
+__global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, uint32_t* cursor,
                                                     uint2* __restrict__ rec_all, uint32_t* ctr) {
   __shared__ uint32_t s_next;
   constexpr int kPer = kScatterPer;
@@ -309,7 +315,9 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* c
   __shared__ uint32_t cnt[kMaxBins / 2];
   __shared__ uint32_t start[kMaxBins / 2];
   __shared__ uint32_t gpos[kMaxBins / 2];
-  __shared__ uint32_t waves[kBlock / kWave];
+  __shared__ uint32_t waves[kScatterThreads / kWave];
+  // bins per thread in the count scan
+  constexpr uint32_t kNpt = (kMaxBins / 2 + kScatterThreads - 1) / kScatterThreads;
   const uint32_t per_cube = d.S * d.R;   // bins of one cube (<= 1024)
   uint2 p[kPer];
   auto load = [&](uint32_t gc) {
@@ -319,7 +327,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* c
     const uint2* src = st.pairs + lo;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
-      const uint32_t k = threadIdx.x + u * kBlock;
+      const uint32_t k = threadIdx.x + u * kScatterThreads;
       p[u] = k < rem ? src[k] : make_uint2(0u, 0u);
     }
   };
@@ -342,7 +350,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* c
     const int side = st.side;
 #pragma unroll
     for (int k = 0; k < (TWO ? 2 : 1); ++k) {
-      for (uint32_t i = threadIdx.x; i < per_cube; i += kBlock) cnt[i] = 0;
+      for (uint32_t i = threadIdx.x; i < per_cube; i += kScatterThreads) cnt[i] = 0;
       __syncthreads();
       uint32_t rk[(kPer + 1) / 2];
 #pragma unroll
@@ -353,21 +361,37 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* c
         const uint32_t p0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].y : p[u].x) : p[u].x;
         uint2 r;
         const uint32_t bl = bin_of(d, k, h0, p0, r) - k * per_cube;
-        const uint32_t rank = threadIdx.x + u * kBlock < rem ? atomicAdd(&cnt[bl], 1u) : kNoRank;
+        const uint32_t rank = threadIdx.x + u * kScatterThreads < rem ? atomicAdd(&cnt[bl], 1u) : kNoRank;
         rk[u / 2] = pack_rank(rk[u / 2], u, rank);
       }
       __syncthreads();
-      // local runs (exclusive prefix of the counts) and global runs (one
-      // atomic add per non-empty bin on the stream's cursor)
-      const uint32_t c0 = threadIdx.x < per_cube ? cnt[threadIdx.x] : 0u;
+      // local runs (exclusive prefix of the counts, kNpt consecutive bins per
+      // thread) and global runs (one atomic add per non-empty bin on the
+      // stream's cursor; a thread's adds are in flight together)
+      uint32_t c[kNpt], g[kNpt], sum = 0;
+#pragma unroll
+      for (uint32_t j = 0; j < kNpt; ++j) {
+        const uint32_t i = threadIdx.x * kNpt + j;
+        c[j] = i < per_cube ? cnt[i] : 0u;
+        sum += c[j];
+      }
+#pragma unroll
+      for (uint32_t j = 0; j < kNpt; ++j) {
+        const uint32_t i = threadIdx.x * kNpt + j;
+        g[j] = c[j] ? __hip_atomic_fetch_add(cur + k * per_cube + i, c[j], __ATOMIC_RELAXED,
+                                             __HIP_MEMORY_SCOPE_AGENT)
+                    : 0u;
+      }
       uint32_t total;
-      const uint32_t ex = block_exclusive_scan(c0, waves, total);
-      if (threadIdx.x < per_cube) {
-        start[threadIdx.x] = ex;
-        gpos[threadIdx.x] =
-            c0 ? __hip_atomic_fetch_add(cur + k * per_cube + threadIdx.x, c0, __ATOMIC_RELAXED,
-                                        __HIP_MEMORY_SCOPE_AGENT)
-               : 0u;
+      uint32_t run = block_exclusive_scan<kScatterThreads>(sum, waves, total);
+#pragma unroll
+      for (uint32_t j = 0; j < kNpt; ++j) {
+        const uint32_t i = threadIdx.x * kNpt + j;
+        if (i < per_cube) {
+          start[i] = run;
+          gpos[i] = g[j];
+        }
+        run += c[j];
       }
       __syncthreads();
 #pragma unroll
@@ -387,7 +411,7 @@ __global__ __launch_bounds__(kBlock) void k_scatter(Dims d, Batch b, uint32_t* c
         gc_cur = s_next;
         if (gc_cur < b.total_schunks) load(gc_cur);
       }
-      for (uint32_t t = threadIdx.x; t < total; t += kBlock) {
+      for (uint32_t t = threadIdx.x; t < total; t += kScatterThreads) {
         const uint2 v = stage[t];
         const uint32_t bl = bin_of_record(d, v) - k * per_cube;
         rec[gpos[bl] + (t - start[bl])] = v;
@@ -548,7 +572,8 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
     if ((rc = check("clear launch")) != CBAA_OK) return rc;
   }
   const uint32_t sgrid = b.total_schunks < kScatterBlocks ? b.total_schunks : kScatterBlocks;
-  hipLaunchKernelGGL((k_scatter<TWO>), dim3(sgrid), dim3(kBlock), 0, s, d, b, L.cursor, L.rec, L.next + 1);
+  hipLaunchKernelGGL((k_scatter<TWO>), dim3(sgrid), dim3(kScatterThreads), 0, s, d, b, L.cursor,
+                     L.rec, L.next + 1);
   if ((rc = check("scatter launch")) != CBAA_OK) return rc;
   return run_apply(d, b, L, apply_blocks, s);
 }

@@ -30,11 +30,7 @@ __global__ __launch_bounds__(kBlock) void k_cube_init(Dims d, uint64_t* bits) {
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride)
     p[i] = make_uint4(0u, 0u, 0u, 0u);
-  if (blockIdx.x == 0 && threadIdx.x < kHeaderWords) {
-    uint64_t* h = header_of(bits);
-    if (threadIdx.x == 0) header_set(h, d, CBAA_CUBE_VALID);
-    if (threadIdx.x >= 4) h[threadIdx.x] = 0;
-  }
+  if (blockIdx.x == 0 && threadIdx.x == 0) header_set(header_of(bits), d, CBAA_CUBE_VALID);
 }
 
 // The direct path's cubes keep a valid header only if they have one.

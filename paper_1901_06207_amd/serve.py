@@ -1,19 +1,31 @@
 """Serving loop for edge-router packet streams (continuous batching).
 
-Each router's cubes stay resident in HBM for the whole window. Packet chunks
-arrive (from pinned host memory) at any time; a chunk is admitted when a
-staging region of its size is free in a fixed device budget (admission by
-memory), its copy to the device runs on a copy stream, and every chunk whose
-copy has finished joins the next batched update (``cbaa_update_batch``) on
-one of two compute streams -- so copies, and successive batches, overlap on
-the device while new chunks keep arriving. A chunk's latency runs from its
-arrival to the completion of the batch that took it. At window end the
-routers' cubes are OR-merged into the global cubes and both are restored
-(the global server of the paper's distributed model), then the routers'
-cubes are zeroed for the next window.
+The global server of the paper's distributed model (Sec. 2, Sec. 3.3) keeps
+the local cubes of the edge routers that are sending in HBM and serves their
+packet chunks as they arrive:
+
+* Admission by memory, twice. A chunk is admitted when a staging region of
+  its size is free in a fixed device budget; its router's cubes must be
+  resident, inside a second budget for cubes. A router that is not resident
+  gets cubes when the cube budget has room; otherwise the least recently used
+  resident router with no work in flight is retired: its cubes are OR-merged
+  into the window's global cubes (Sec. 3.3: the merge is a bitwise OR, so
+  merging a router early, or twice, changes nothing) and freed. A chunk whose
+  router cannot be made resident yet waits.
+* Continuous batching. An admitted chunk's copy to the device runs on a copy
+  stream; every chunk whose copy has finished joins the next batched update
+  (``cbaa_update_batch``) on one of two compute streams, so copies, updates
+  and new arrivals overlap on the device.
+* Window end. The global cubes, holding the retired routers, and the resident
+  routers' cubes are OR-merged and restored in one call per side; the
+  resident cubes start the next window empty.
+
+Latencies: a chunk's update latency runs from its arrival to the completion of
+the batch that took it; its result latency from its arrival to the moment the
+restored lists of its window are on the host.
 
 All arithmetic is in libcbaa's kernels; this module schedules, allocates
-staging space and records times.
+staging and cube memory, and records times.
 """
 
 from __future__ import annotations
@@ -77,12 +89,14 @@ class Chunk:
     nbytes: int = 0
     copied: Optional[torch.cuda.Event] = None
     t_done: float = 0.0
+    t_result: float = 0.0
 
 
 class Server:
     def __init__(self, cfg, n_routers: int, both_sides: bool = True,
-                 staging_bytes: int = 512 << 20, max_batch: int = cbaa.MAX_BATCH,
-                 capacity: int = 1 << 14, theta: float = 1024.0, tuning=None, device="cuda"):
+                 staging_bytes: int = 512 << 20, cube_budget_bytes: Optional[int] = None,
+                 max_batch: int = cbaa.MAX_BATCH, capacity: int = 1 << 14,
+                 theta: float = 1024.0, tuning=None, device="cuda"):
         self.cfg = cfg
         self.dev = torch.device(device)
         self.nr = n_routers
@@ -90,10 +104,23 @@ class Server:
         self.theta = theta
         self.max_batch = max_batch
         self.tuning = tuning
-        self.cubes = [(cbaa.new_cube(cfg, self.dev), cbaa.new_cube(cfg, self.dev) if both_sides else None)
-                      for _ in range(n_routers)]
-        self.g_src = cbaa.new_cube(cfg, self.dev, init=False)
-        self.g_dst = cbaa.new_cube(cfg, self.dev, init=False) if both_sides else None
+        self.per_router = cbaa.cbaa_cube_bytes(cfg) * (2 if both_sides else 1)
+        # by default every router fits: the budget only bites when it is given
+        self.cube_budget = (cube_budget_bytes if cube_budget_bytes is not None
+                            else n_routers * self.per_router)
+        if self.cube_budget < self.per_router:
+            raise ValueError("the cube budget holds no router's cubes")
+        self.cubes = {}                          # resident router -> (src cube, dst cube or None)
+        self.cube_used = 0
+        self.cube_peak = 0
+        self.inflight_of = collections.Counter()  # router -> chunks admitted, not yet updated
+        self.last_use = {}                       # router -> admission tick (LRU)
+        self.tick = 0
+        self.retirements = 0
+        self.retired_this_window = False
+        self.graveyard = []                      # (event, tensors) freed once the event completes
+        self.g_src = cbaa.new_cube(cfg, self.dev)
+        self.g_dst = cbaa.new_cube(cfg, self.dev) if both_sides else None
         self.staging = torch.empty(staging_bytes, dtype=torch.uint8, device=self.dev)
         self.alloc = StagingAllocator(staging_bytes)
         # scratch for the largest batch the staging can hold, any split over streams
@@ -111,6 +138,7 @@ class Server:
         self.copying = []                       # admitted, copy in flight
         self.inflight = []                      # (event, chunks, stream index)
         self.done = []
+        self.last_event = {}                    # router -> event of its last batch
         self.next_compute = 0
         self.batches = 0
         self.packets = 0
@@ -122,7 +150,8 @@ class Server:
         import ctypes as C
         k = self.max_batch
         dummy = torch.empty((1, 2), dtype=torch.int32, device=self.dev)
-        a, b = self.cubes[0]
+        a = cbaa.new_cube(self.cfg, self.dev, init=False)
+        b = cbaa.new_cube(self.cfg, self.dev, init=False) if self.both else None
         splits = [[max_pairs]]
         per = 65537   # one pair over a chunk: two chunks per stream
         if per * (k - 1) < max_pairs:
@@ -137,16 +166,76 @@ class Server:
                 C.byref(cbaa._cfg(self.cfg)), table, len(sizes),
                 C.byref(cbaa._tuning(self.tuning)) if self.tuning else None)
             best = max(best, int(need))
+        del a, b
         return best
 
     # ---- request side ------------------------------------------------------
     def submit(self, router: int, host_pairs: torch.Tensor, t_arrival: Optional[float] = None) -> int:
         """Queues a chunk of (source, destination) pairs held in pinned host
         memory (int32 [n, 2] storage of the uint32 addresses) for router."""
+        if not 0 <= router < self.nr:
+            raise ValueError(f"router {router} outside [0, {self.nr})")
         cid = self.submitted
         self.submitted += 1
         self.waiting.append(Chunk(cid, router, host_pairs, t_arrival or time.perf_counter()))
         return cid
+
+    # ---- cube residency ------------------------------------------------------
+    def _bury(self, stream, tensors) -> None:
+        ev = torch.cuda.Event()
+        ev.record(stream)
+        self.graveyard.append((ev, tensors))
+
+    def _reap(self, block: bool = False) -> None:
+        keep = []
+        for ev, tensors in self.graveyard:
+            if block:
+                ev.synchronize()
+            if ev.query():
+                self.cube_used -= self.per_router
+            else:
+                keep.append((ev, tensors))
+        self.graveyard = keep
+
+    def _retire(self, r: int) -> None:
+        """OR-merges router r's cubes into the global cubes and frees them."""
+        a, b = self.cubes.pop(r)
+        st = self.compute[0]
+        ev = self.last_event.pop(r, None)
+        if ev is not None:
+            st.wait_event(ev)
+        # merges run on one stream, so they are ordered among themselves; only
+        # the window end reads the global cubes, after a full synchronisation
+        cbaa.cbaa_merge_or(self.cfg, self.g_src, [self.g_src, a], st)
+        if b is not None:
+            cbaa.cbaa_merge_or(self.cfg, self.g_dst, [self.g_dst, b], st)
+        self._bury(st, (a, b))
+        self.retirements += 1
+        self.retired_this_window = True
+
+    def _make_resident(self, r: int) -> bool:
+        if r in self.cubes:
+            return True
+        self._reap()
+        while self.cube_used + self.per_router > self.cube_budget:
+            idle = [x for x in self.cubes if self.inflight_of[x] == 0]
+            if not idle:
+                if self.graveyard:          # cubes being freed: wait for them
+                    self._reap(block=True)
+                    continue
+                return False
+            self._retire(min(idle, key=lambda x: self.last_use.get(x, -1)))
+            self._reap()
+            if self.cube_used + self.per_router > self.cube_budget and self.graveyard:
+                self._reap(block=True)
+        st = self.compute[self.next_compute]
+        a = cbaa.new_cube(self.cfg, self.dev, stream=st)
+        b = cbaa.new_cube(self.cfg, self.dev, stream=st) if self.both else None
+        self.compute[self.next_compute ^ 1].wait_stream(st)
+        self.cubes[r] = (a, b)
+        self.cube_used += self.per_router
+        self.cube_peak = max(self.cube_peak, self.cube_used)
+        return True
 
     # ---- scheduling ----------------------------------------------------------
     def _admit(self) -> None:
@@ -155,11 +244,16 @@ class Server:
             nbytes = int(c.host.shape[0]) * 8
             if nbytes > self.alloc.size:
                 raise ValueError("chunk larger than the staging budget")
+            if not self._make_resident(c.router):
+                return
             off = self.alloc.alloc(nbytes)
             if off is None:
                 return
             self.waiting.popleft()
             c.off, c.nbytes = off, nbytes
+            self.tick += 1
+            self.last_use[c.router] = self.tick
+            self.inflight_of[c.router] += 1
             dst = self.staging[off:off + nbytes].view(torch.int32).view(-1, 2)
             with torch.cuda.stream(self.copy):
                 dst.copy_(c.host, non_blocking=True)
@@ -187,10 +281,12 @@ class Server:
         cbaa.cbaa_update_batch(self.cfg, table, self.scratch[i], self.tuning, st)
         ev = torch.cuda.Event()
         ev.record(st)
+        for c in ready:
+            self.last_event[c.router] = ev
         self.inflight.append((ev, ready, i))
         self.batches += 1
 
-    def _retire(self, block: bool = False) -> None:
+    def _complete(self, block: bool = False) -> None:
         keep = []
         for ev, chunks, i in self.inflight:
             if block:
@@ -200,6 +296,7 @@ class Server:
                 for c in chunks:
                     c.t_done = now
                     self.alloc.release(c.off, c.nbytes)
+                    self.inflight_of[c.router] -= 1
                     self.packets += int(c.host.shape[0])
                     self.done.append(c)
             else:
@@ -207,46 +304,64 @@ class Server:
         self.inflight = keep
 
     def poll(self) -> None:
-        self._retire()
+        self._complete()
+        self._reap()
         self._admit()
         self._launch()
 
     def drain(self) -> None:
         while self.waiting or self.copying or self.inflight:
             self.poll()
-            if self.inflight and not self.copying and not self.waiting:
-                self._retire(block=True)
+            if self.inflight and not self.copying:
+                self._complete(block=True)
 
     # ---- window end (global server) ----------------------------------------------
     def end_window(self, reset: bool = True) -> dict:
-        """Drains, OR-merges the routers' cubes, restores the global cubes and
-        (unless reset is False) zeroes the routers' cubes. Returns host lists
-        and timings."""
+        """Drains, OR-merges the retired routers (held in the global cubes) and
+        the resident routers' cubes, restores both sides and (unless reset is
+        False) starts the next window from empty cubes. Returns host lists and
+        timings; every chunk of the window gets its result time."""
         self.drain()
         torch.cuda.synchronize(self.dev)
         t0 = time.perf_counter()
         s = torch.cuda.current_stream(self.dev)
-        cubes = [self.g_src] + ([self.g_dst] if self.both else [])
-        for i, g in enumerate(cubes):   # per side: OR-merge and restore in one call
-            cbaa.cbaa_merge_restore(self.cfg, g, [c[i] for c in self.cubes], self.theta,
-                                    cbaa.THR_THM2, self.rs[i], self.outs[i], self.capacity,
-                                    self.stats[i], s)
-        for a, b in self.cubes if reset else []:
-            cbaa.cbaa_cube_init(self.cfg, a, s)
-            if b is not None:
-                cbaa.cbaa_cube_init(self.cfg, b, s)
+        glob = [self.g_src] + ([self.g_dst] if self.both else [])
+        routers = sorted(self.cubes)
+        for i, g in enumerate(glob):   # per side: OR-merge and restore in one call
+            srcs = ([g] if self.retired_this_window else []) + [self.cubes[r][i] for r in routers]
+            if not srcs:
+                srcs = [g]
+            cbaa.cbaa_merge_restore(self.cfg, g, srcs, self.theta, cbaa.THR_THM2, self.rs[i],
+                                    self.outs[i], self.capacity, self.stats[i], s)
+        if reset:
+            for r in routers:
+                for c in self.cubes[r]:
+                    if c is not None:
+                        cbaa.cbaa_cube_init(self.cfg, c, s)
+            for g in glob:
+                cbaa.cbaa_cube_init(self.cfg, g, s)
+            self.retired_this_window = False
         torch.cuda.synchronize(self.dev)
-        t1 = time.perf_counter()
         lists = []
-        for i in range(len(cubes)):
+        for i in range(len(glob)):
             n = int(self.stats[i][0])
             if n > self.capacity:
                 raise RuntimeError(f"restore capacity {self.capacity} below {n}")
             lists.append(cbaa.host_list(self.outs[i], n))
+        t1 = time.perf_counter()
+        for c in self.done:
+            if not c.t_result:
+                c.t_result = t1
+        self._reap(block=True)
         return {"hosts": lists, "restore_ms": (t1 - t0) * 1e3}
 
     def latencies_ms(self) -> np.ndarray:
+        """Update latency of every finished chunk: arrival to its batch done."""
         return np.array([(c.t_done - c.t_arrival) * 1e3 for c in self.done])
+
+    def result_latencies_ms(self) -> np.ndarray:
+        """Result latency: arrival to its window's restored lists on the host."""
+        return np.array([(c.t_result - c.t_arrival) * 1e3 for c in self.done if c.t_result])
 
 
 def poisson_schedule(n_routers: int, window_s: float, chunk_lo: int, chunk_hi: int,
@@ -284,10 +399,14 @@ def run_window(server: Server, events, chunks_host, time_scale: float) -> dict:
     t_last = time.perf_counter()
     res = server.end_window()
     lat = server.latencies_ms()
+    rlat = server.result_latencies_ms()
     pk = sum(int(c.host.shape[0]) for c in server.done)
     res.update({"chunks": len(server.done), "packets": pk, "wall_s": t_last - t0,
                 "gpkt_s": pk / max(t_last - t0, 1e-9) / 1e9,
                 "p50_ms": float(np.percentile(lat, 50)) if lat.size else 0.0,
                 "p99_ms": float(np.percentile(lat, 99)) if lat.size else 0.0,
-                "staging_peak_bytes": server.alloc.peak, "batches": server.batches})
+                "result_p50_ms": float(np.percentile(rlat, 50)) if rlat.size else 0.0,
+                "result_p99_ms": float(np.percentile(rlat, 99)) if rlat.size else 0.0,
+                "staging_peak_bytes": server.alloc.peak, "batches": server.batches,
+                "cube_peak_bytes": server.cube_peak, "retirements": server.retirements})
     return res

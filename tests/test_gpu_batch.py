@@ -235,3 +235,61 @@ def test_autotuner_picks_a_valid_shape(cb):
     torch.cuda.synchronize()
     for q, c in zip(parts, cubes):
         assert np.array_equal(cb.cube_to_numpy(c), O.cube_of(p, q, 0))
+
+
+def test_batch_of_32_streams_with_a_64mi_stream(cb):
+    """CBAA_MAX_BATCH streams in one call: uneven sizes from empty to a full
+    64Mi-packet core-edge window, both cubes per stream, fresh streams that own
+    their cubes next to OR-ing streams that share two cube pairs holding earlier
+    bits. Every cube equals the oracle's (fresh: the stream's own pairs; shared:
+    the earlier bits OR-ed with every stream's pairs)."""
+    import torch
+    p = default_params()
+    assert cb.MAX_BATCH == 32
+    rng = np.random.default_rng(32)
+    sizes = [int(x) for x in np.exp(rng.uniform(np.log(2_000), np.log(1_500_000), 31))]
+    sizes[3], sizes[17] = 0, 1
+    print("[case] batch of 32 streams, one of 64Mi packets", flush=True)
+    parts = _streams(32, sizes)
+    big = tracegen.window_core_edge(14).pairs          # 64 x 2^20 packets
+    parts.insert(9, big)
+    fresh_idx = [0, 9, 20, 31]                          # own their cubes, start empty
+    shared = [(cb.new_cube(p), cb.new_cube(p)) for _ in range(2)]
+    # earlier bits in the shared cubes
+    prior = _streams(99, [200_000, 150_000])
+    for (a, b), q in zip(shared, prior):
+        cb.cbaa_update2(p, a, b, cb.pairs_to_device(q))
+    own = {}
+    table = []
+    for i, q in enumerate(parts):
+        d = cb.pairs_to_device(q) if len(q) else torch.zeros((0, 2), dtype=torch.int32,
+                                                             device="cuda")
+        if i in fresh_idx:
+            a, b = cb.new_cube(p, init=False), cb.new_cube(p, init=False)
+            a.fill_(-1)                                  # stale content the call must overwrite
+            b.fill_(-1)
+            own[i] = (a, b)
+            table.append((d, a, b, cb.SIDE_SRC, cb.BATCH_FRESH))
+        else:
+            a, b = shared[i % 2]
+            table.append((d, a, b, cb.SIDE_SRC, 0))
+    assert len(table) == 32
+    scratch = cb.scratch_tensor(cb.cbaa_update_batch_scratch_bytes(p, table))
+    cb.cbaa_update_batch(p, table, scratch)
+    torch.cuda.synchronize()
+    del scratch, table
+    for i in fresh_idx:
+        a, b = own[i]
+        for side, cube in ((0, a), (1, b)):
+            want = O.new_cube(p)
+            O.update_omp(p, want, parts[i], side)
+            assert np.array_equal(cb.cube_to_numpy(cube), want), (i, side)
+        assert cb.cbaa_cube_check(p, a) == cb.CBAA_OK
+    for j, (a, b) in enumerate(shared):
+        for side, cube in ((0, a), (1, b)):
+            want = O.new_cube(p)
+            O.update_omp(p, want, prior[j], side)
+            for i, q in enumerate(parts):
+                if i not in fresh_idx and i % 2 == j:
+                    O.update_omp(p, want, q, side)
+            assert np.array_equal(cb.cube_to_numpy(cube), want), (j, side)

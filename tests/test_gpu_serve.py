@@ -1,7 +1,9 @@
 """Serving loop: continuous batching with admission by memory. Every router's
 cube and the restored lists are identical whether its chunks run alone or in
-the mix with other routers' chunks (bit-exact: the cube is a set union), the
-staging budget is never exceeded, and latencies are recorded."""
+the mix with other routers' chunks (bit-exact: the cube is a set union); with
+a cube budget smaller than the routers, routers are retired into the global
+cubes and re-admitted and the lists still equal the oracle's; neither budget is
+ever exceeded, and latencies are recorded."""
 
 import numpy as np
 import pytest
@@ -88,6 +90,33 @@ def test_admission_by_memory_and_latency(cb):
     assert 0 < srv.alloc.peak <= budget
     assert res["p99_ms"] >= res["p50_ms"] > 0
     # next window starts from emptied cubes that carry a valid header
-    for a, _ in srv.cubes:
+    for a, _ in srv.cubes.values():
         assert int(a[cb.HEADER_WORDS:].abs().sum()) == 0
         assert cb.cbaa_cube_check(p, a) == 0
+
+
+def test_cube_budget_retires_routers_and_keeps_results(cb):
+    """Six routers, cubes for two: routers are retired (OR-merged into the
+    global cubes, freed) and re-admitted when they send again; two windows in a
+    row give the oracle's lists of each window's traffic."""
+    from paper_1901_06207_amd import serve
+    p = default_params()
+    per = 2 * cb.cbaa_cube_bytes(p)
+    srv = serve.Server(p, 6, both_sides=True, staging_bytes=8 << 20, cube_budget_bytes=2 * per)
+    for w in range(2):
+        print(f"[case] serving window {w} with a two-router cube budget", flush=True)
+        chunks = _chunks(6, 4, 20_000, 200_000, seed=41 + w)
+        events = [(0.0002 * i, r, len(q)) for i, (r, q, _) in enumerate(chunks)]
+        before = srv.retirements
+        res = serve.run_window(srv, events, [h for _, _, h in chunks], time_scale=1.0)
+        assert res["chunks"] == len(chunks)
+        assert srv.retirements > before
+        assert 0 < res["cube_peak_bytes"] <= 2 * per
+        assert res["result_p99_ms"] >= res["result_p50_ms"] >= res["p50_ms"] > 0
+        allq = np.concatenate([q for _, q, _ in chunks])
+        for side in (0, 1):
+            want, _ = O.restore(p, O.cube_of(p, allq, side), 1024.0)
+            got = res["hosts"][side]
+            assert np.array_equal(got["ip"], want["ip"]), (w, side)
+            assert np.array_equal(got["zeros"], want["zeros"])
+            assert got.size > 0
