@@ -43,11 +43,11 @@ HBM_PEAK_GBS = 8000.0
 # tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
 # valid only while the update kernels' sources are the ones measured
 # (profiles/update_core_edge_64M_traffic.txt).
-UPDATE_TRAFFIC = {"bytes": 4051983283, "sources": {
+UPDATE_TRAFFIC = {"bytes": 4039025391, "sources": {
     "paper_1901_06207_amd/csrc/cbaa_partition.hip":
-        "cdb6598fcf7d5dc52bbe9fc10881a540339c4a818082b21ec0e80bb94eedd4e0",
+        "dbe08ac0c88b2976d6bcf520c4f61fe550356c8b80fdab2d6dc77f35fedb033d",
     "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
-        "84680ce1736e72de2064e9eeec6e3166ce2dac8f9f0a71f0de6cf8e23126c5cb"}}
+        "6f403f6d6f8c1be7f01b02e96da5676cf36826744c3bbdc98ea5754fd46e6bdd"}}
 
 
 def measured_traffic(record, default_workload):
@@ -87,6 +87,9 @@ def parse():
     ap.add_argument("--update-streams", choices=["one", "per-router"], default="one",
                     help="one: all routers' packets in one batched update call; per-router: "
                          "each router's batch on its own stream, overlapping on the device")
+    ap.add_argument("--window-end-streams", choices=["one", "per-side"], default="per-side",
+                    help="per-side: the two global cubes' merge and restore run on two streams "
+                         "and overlap (one side's scan with the other's tuple check)")
     ap.add_argument("--store-merged", action="store_true",
                     help="the window end also stores each side's merged (global) cube")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -195,10 +198,21 @@ def main():
         # The merged cube is an intermediate of the restore: unless asked to,
         # it is not stored, and the restore reads each column it needs as the
         # OR of the router cubes.
+        if per_side:
+            fork = torch.cuda.Event()
+            fork.record(stream)
         for i, cube in enumerate((g_src, g_dst)):
+            st = wstreams[i] if per_side else stream
+            if per_side:
+                st.wait_event(fork)
             cbaa.cbaa_merge_restore(cfg, cube if args.store_merged else None,
                                     [x[i] for x in local], args.theta, cbaa.THR_THM2,
-                                    scratch_r[i], outs[i], capacity, stats[i], stream)
+                                    scratch_r[i], outs[i], capacity, stats[i], st)
+        if per_side:
+            for st in wstreams:
+                e = torch.cuda.Event()
+                e.record(st)
+                stream.wait_event(e)
         if timed:
             mark("copy", stream)
         with torch.cuda.stream(stream):
@@ -207,6 +221,9 @@ def main():
             mark("end", stream)
 
     stream = torch.cuda.Stream(device=dev)
+    # the two sides' window ends are independent (one global cube each)
+    per_side = args.window_end_streams == "per-side"
+    wstreams = [torch.cuda.Stream(device=dev) for _ in range(2)] if per_side else []
     for _ in range(args.warmup):
         step(stream)
     torch.cuda.synchronize(dev)
@@ -389,6 +406,7 @@ def main():
             "packets": trace.n, "routers": args.routers, "seed": args.seed,
             "launch": "eager" if graph is None else "hip-graph",
             "update_streams": args.update_streams if len(parts) > 1 else "one",
+            "window_end_streams": args.window_end_streams,
             "tuning": tuning or "default",
             "merged_cube": ("stored" if args.store_merged else
                             "not stored: the restore reads columns as the OR of the router cubes"),
@@ -397,6 +415,7 @@ def main():
             "update_ms": round(float(upd_ms.mean()), 4),
             "update_gpkt_s": round(float(upd_gpkts), 3),
             "window_end_ms_per_side": round(float(window_end_ms.mean()), 4),
+            "window_end_ms_both_sides": round(float(window_end_ms.mean()) * 2.0, 4),
             ("window_end_unstored_ms_per_side" if args.store_merged
              else "window_end_stored_ms_per_side"): round(float(window_end_other_ms.mean()), 4),
             "merge_ms": round(float(merge_ms.mean()), 4),
@@ -842,7 +861,7 @@ def bench_learned(cfg, trace, g_src, local, dev, args):
         cbaa.cbaa_update(cfg, cube, cbaa.pairs_to_device(tw.pairs, dev), cbaa.SIDE_SRC, sc)
         del sc
         hosts, counts = tracegen.construction_truth(tw, 0)
-        idx = learned.stratified_rows(counts, 700_000, rng)
+        idx = learned.stratified_rows(counts, 1_000_000, rng)
         xs.append(learned.features(cfg, cube, hosts[idx]))
         ts.append(torch.from_numpy(np.log1p(counts[idx]).astype(np.float32)).to(dev))
         del cube, tw, hosts, counts
