@@ -39,16 +39,22 @@ namespace cbaa {
 namespace {
 
 constexpr int kBlock = 1024;
-constexpr uint32_t kMaxBins = 2048;
+constexpr uint32_t kMaxBins = 8192;      // bins of a stream (both cubes)
 constexpr int kUnroll = 8;                // independent loads in flight per thread
 constexpr int kApplyUnroll = 16;
 constexpr uint32_t kMaxTileWords = 16384; // 128 KiB LDS tile
 // Scatter blocks of 768 threads (12 waves) have 168 registers per lane: a
 // chunk of 20 pairs per thread stays in registers with no spill, and its
-// 8-byte records fill 120 KiB of LDS.
+// 8-byte records fill 120 KiB of LDS next to 12 KiB of counters for up to
+// 1024 bins per cube. Cubes of up to 4096 bins (e.g. 32 sketches, or
+// 8192-bit columns) take 18 pairs per thread beside 48 KiB of counters.
 constexpr int kScatterThreads = 768;
-constexpr int kScatterPer = 20;           // pairs per thread in a scatter chunk
-constexpr uint32_t kScatterChunk = kScatterPer * kScatterThreads;
+constexpr uint32_t kSmallBins = 1024;     // bins per cube of the first shape
+constexpr int kScatterPerSmall = 20;
+constexpr int kScatterPerLarge = 18;
+inline uint32_t scatter_chunk(uint32_t per_cube) {
+  return (per_cube <= kSmallBins ? kScatterPerSmall : kScatterPerLarge) * kScatterThreads;
+}
 constexpr uint32_t kScatterBlocks = 256;  // persistent scatter grid (one per CU)
 constexpr uint32_t kDefaultChunk = 65536;
 constexpr uint32_t kDefaultSeg = 65536;
@@ -75,6 +81,7 @@ struct Batch {
   uint32_t total_chunks;  // histogram chunks of all streams
   uint32_t total_schunks; // scatter chunks of all streams
   uint32_t chunk;         // pairs per histogram chunk
+  uint32_t schunk;        // pairs per scatter chunk
   uint32_t seg;           // records per apply item
   StreamDesc s[CBAA_MAX_BATCH];
 };
@@ -106,6 +113,7 @@ Tuning effective(const cbaa_tuning* t) {
 Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
   b.nbins = (uint32_t)n_cubes * d.S * d.R;
   b.chunk = chunk;
+  b.schunk = scatter_chunk(d.S * d.R);
   uint32_t ch = 0, sch = 0;
   uint64_t rec = 0;
   for (uint32_t i = 0; i < b.k; ++i) {
@@ -114,7 +122,7 @@ Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
     s.schunk_begin = sch;
     s.rec_base = rec;
     ch += (uint32_t)((s.n + chunk - 1) / chunk);
-    sch += (uint32_t)((s.n + kScatterChunk - 1) / kScatterChunk);
+    sch += (uint32_t)((s.n + b.schunk - 1) / b.schunk);
     rec += (uint64_t)n_cubes * s.n;
   }
   b.total_chunks = ch;
@@ -305,20 +313,21 @@ __device__ inline uint32_t pack_rank(uint32_t rk, int u, uint32_t rank) {
 
 __device__ inline uint32_t unpack_rank(uint32_t rk, int u) { return (rk >> (16 * (u & 1))) & 0xFFFFu; }
 
-template <bool TWO>
+// NB: the most bins per cube the LDS counters hold; PER: pairs per thread.
+template <bool TWO, uint32_t NB, int PER>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, uint32_t* cursor,
                                                     uint2* __restrict__ rec_all, uint32_t* ctr) {
   __shared__ uint32_t s_next;
-  constexpr int kPer = kScatterPer;
-  constexpr uint32_t P = kScatterChunk;
+  constexpr int kPer = PER;
+  constexpr uint32_t P = PER * kScatterThreads;
   __shared__ uint2 stage[P];
-  __shared__ uint32_t cnt[kMaxBins / 2];
-  __shared__ uint32_t start[kMaxBins / 2];
-  __shared__ uint32_t gpos[kMaxBins / 2];
+  __shared__ uint32_t cnt[NB];
+  __shared__ uint32_t start[NB];
+  __shared__ uint32_t gpos[NB];
   __shared__ uint32_t waves[kScatterThreads / kWave];
   // bins per thread in the count scan
-  constexpr uint32_t kNpt = (kMaxBins / 2 + kScatterThreads - 1) / kScatterThreads;
-  const uint32_t per_cube = d.S * d.R;   // bins of one cube (<= 1024)
+  constexpr uint32_t kNpt = (NB + kScatterThreads - 1) / kScatterThreads;
+  const uint32_t per_cube = d.S * d.R;   // bins of one cube (<= NB)
   uint2 p[kPer];
   auto load = [&](uint32_t gc) {
     const StreamDesc& st = b.s[owner_of_schunk(b, gc)];
@@ -572,8 +581,12 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
     if ((rc = check("clear launch")) != CBAA_OK) return rc;
   }
   const uint32_t sgrid = b.total_schunks < kScatterBlocks ? b.total_schunks : kScatterBlocks;
-  hipLaunchKernelGGL((k_scatter<TWO>), dim3(sgrid), dim3(kScatterThreads), 0, s, d, b, L.cursor,
-                     L.rec, L.next + 1);
+  if (d.S * d.R <= kSmallBins)
+    hipLaunchKernelGGL((k_scatter<TWO, kSmallBins, kScatterPerSmall>), dim3(sgrid),
+                       dim3(kScatterThreads), 0, s, d, b, L.cursor, L.rec, L.next + 1);
+  else
+    hipLaunchKernelGGL((k_scatter<TWO, kMaxBins / 2, kScatterPerLarge>), dim3(sgrid),
+                       dim3(kScatterThreads), 0, s, d, b, L.cursor, L.rec, L.next + 1);
   if ((rc = check("scatter launch")) != CBAA_OK) return rc;
   return run_apply(d, b, L, apply_blocks, s);
 }

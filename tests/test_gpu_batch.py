@@ -293,3 +293,32 @@ def test_batch_of_32_streams_with_a_64mi_stream(cb):
                 if i not in fresh_idx and i % 2 == j:
                     O.update_omp(p, want, q, side)
             assert np.array_equal(cb.cube_to_numpy(cube), want), (j, side)
+
+
+@pytest.mark.parametrize("dims", [dict(r=5, cl_bs=[5, 14, 23]), dict(log2_g=13),
+                                  dict(r=5, cl_bs=[5, 14, 23], log2_g=13)])
+def test_batch_with_up_to_4096_bins_per_cube(cb, dims):
+    """Cubes of 2048 and 4096 bins per cube (32 sketches, 8192-bit columns,
+    both) take the partitioned path's second shape (18 pairs per thread
+    beside larger LDS counters): both cubes of uneven streams, fresh and
+    OR-ing, bit-exact against the oracle."""
+    import torch
+    p = dict(default_params(), **dims)
+    assert cb.cbaa_update_scratch_bytes(p, 1 << 20, 2) > 0      # partitioned, not direct
+    print("[case] batch with", dims, flush=True)
+    parts = _streams(77, [400_000, 0, 1_300_000, 70_001])
+    table, cubes = [], []
+    for i, q in enumerate(parts):
+        a, b = cb.new_cube(p), cb.new_cube(p)
+        if i == 3:   # an OR-ing stream onto cubes holding earlier bits
+            cb.cbaa_update2(p, a, b, cb.pairs_to_device(parts[0]))
+        cubes.append((a, b))
+        d = cb.pairs_to_device(q) if len(q) else torch.zeros((0, 2), dtype=torch.int32, device="cuda")
+        table.append((d, a, b, cb.SIDE_SRC, 0 if i == 3 else cb.BATCH_FRESH))
+    scratch = cb.scratch_tensor(cb.cbaa_update_batch_scratch_bytes(p, table))
+    cb.cbaa_update_batch(p, table, scratch)
+    torch.cuda.synchronize()
+    for i, (q, (a, b)) in enumerate(zip(parts, cubes)):
+        src = np.concatenate([parts[0], q]) if i == 3 else q
+        assert np.array_equal(cb.cube_to_numpy(a), O.cube_of(p, src, 0)), i
+        assert np.array_equal(cb.cube_to_numpy(b), O.cube_of(p, src, 1)), i
