@@ -9,8 +9,12 @@
  *     z1 = W1 x + b1, h1 = relu(z1); z2 = W2 h1 + b2, h2 = relu(z2);
  *     y = w3 . h2 + b3;  estimate = exp(y) - 1.
  * Hidden width 64; weights W1, W2, w3 are bfloat16, biases fp32, all
- * accumulation fp32. Training minimises mean (y - t)^2 / 2 with Adam on an
- * fp32 master copy of every parameter.
+ * accumulation fp32. z1 is computed in fp32 as b1 plus each input's product
+ * in input order, and the second layer takes h1 rounded to bfloat16 (round to
+ * nearest even), so that its 64 x 64 product is a bf16 contraction: inference
+ * runs it on the matrix cores. Training minimises mean (y - t)^2 / 2 with Adam
+ * on an fp32 master copy of every parameter; the gradient passes the rounding
+ * of h1 unchanged.
  *
  * Parameter vector (fp32 master, P = cbaa_mlp_param_count(F) floats):
  *     W1 [64][F] row-major, b1 [64], W2 [64][64] row-major, b2 [64], w3 [64], b3

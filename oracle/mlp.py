@@ -12,7 +12,13 @@ Network (F inputs, two hidden layers of 64, one output):
     y  = w3 . h2 + b3            (predicts t = ln(1 + n))
     loss = mean over the batch of (y - t)^2 / 2
 Weights W1, W2, w3 are used in bfloat16 (round to nearest even from the fp32
-master copy); biases in fp32. Flat parameter order:
+master copy); biases in fp32. The second layer also takes its inputs in
+bfloat16 (its 64 x 64 product is a bf16 contraction on the device's matrix
+cores): z1 is computed in fp32 as the device does (bias first, then each
+input's product added in input order), and h1 = bf16(relu(z1)) enters z2 and
+the gradient of W2. Everything after that is fp64 here. With act_bf16=False
+the network is the plain fp64 one (used to pin the gradient by finite
+differences). Flat parameter order:
     W1 [64, F] row-major, b1 [64], W2 [64, 64] row-major, b2 [64], w3 [64], b3 [1]
 Features (see ``features``): each array's own linear count of the host's
 column in log form, ln(1 + g u_a) with u_a = -ln(max(z_a, 1)/g), optionally
@@ -97,21 +103,41 @@ def compute_params(master: np.ndarray, F: int) -> np.ndarray:
     return p
 
 
-def forward(theta: np.ndarray, F: int, x: np.ndarray):
+def layer1_fp32(theta: np.ndarray, F: int, x: np.ndarray) -> np.ndarray:
+    """z1 in fp32 in the device's order: b1, then + W1[:, f] * x[:, f] for
+    f = 0, 1, ..., each product and each sum rounded to fp32."""
+    W1, b1 = split(theta, F)[:2]
+    W1 = W1.astype(np.float32)
+    x = np.asarray(x, np.float32)
+    z = np.repeat(b1.astype(np.float32)[None, :], x.shape[0], axis=0)
+    for f in range(F):
+        z = (z + (x[:, f:f + 1] * W1[None, :, f]).astype(np.float32)).astype(np.float32)
+    return z
+
+
+def forward(theta: np.ndarray, F: int, x: np.ndarray, act_bf16: bool = True):
     W1, b1, W2, b2, w3, b3 = (a.astype(np.float64) for a in split(theta, F))
-    x = x.astype(np.float64)
-    z1 = x @ W1.T + b1
-    h1 = np.maximum(z1, 0.0)
+    if act_bf16:
+        z1f = layer1_fp32(theta, F, x)
+        z1 = z1f.astype(np.float64)
+        h1 = to_bf16(np.maximum(z1f, np.float32(0.0))).astype(np.float64)
+        x = np.asarray(x, np.float32).astype(np.float64)
+    else:
+        x = x.astype(np.float64)
+        z1 = x @ W1.T + b1
+        h1 = np.maximum(z1, 0.0)
     z2 = h1 @ W2.T + b2
     h2 = np.maximum(z2, 0.0)
     y = h2 @ w3 + b3[0]
     return y, (x, z1, h1, z2, h2)
 
 
-def loss_and_grad(theta: np.ndarray, F: int, x: np.ndarray, t: np.ndarray):
-    """Mean (y - t)^2 / 2 and its gradient with respect to every parameter."""
+def loss_and_grad(theta: np.ndarray, F: int, x: np.ndarray, t: np.ndarray,
+                  act_bf16: bool = True):
+    """Mean (y - t)^2 / 2 and its gradient with respect to every parameter
+    (with act_bf16, the bf16 rounding of h1 passes gradients unchanged)."""
     W1, b1, W2, b2, w3, b3 = (a.astype(np.float64) for a in split(theta, F))
-    y, (x, z1, h1, z2, h2) = forward(theta, F, x)
+    y, (x, z1, h1, z2, h2) = forward(theta, F, x, act_bf16)
     B = x.shape[0]
     r = y - t.astype(np.float64)
     loss = 0.5 * float(np.mean(r * r))
@@ -140,14 +166,15 @@ def adam_step(master, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
 
 
 def finite_difference_grad(theta, F, x, t, idx, h=1e-6):
-    """Central differences of the loss for the parameters listed in idx."""
+    """Central differences of the fp64 network's loss for the parameters
+    listed in idx."""
     out = []
     for i in idx:
         tp = theta.astype(np.float64).copy()
         tm = tp.copy()
         tp[i] += h
         tm[i] -= h
-        lp, _ = loss_and_grad(tp, F, x, t)
-        lm, _ = loss_and_grad(tm, F, x, t)
+        lp, _ = loss_and_grad(tp, F, x, t, act_bf16=False)
+        lm, _ = loss_and_grad(tm, F, x, t, act_bf16=False)
         out.append((lp - lm) / (2 * h))
     return np.array(out)

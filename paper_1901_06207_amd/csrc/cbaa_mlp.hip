@@ -8,6 +8,13 @@
 // activations live in LDS, and the weight gradients are tile GEMMs
 // (dz^T h) accumulated in registers of the thread that owns each weight, then
 // added to the global gradient once per block.
+//
+// The second layer takes its input activations in bfloat16, like its
+// weights: the 64 x 64 x 64 product of a tile is a dense bf16 contraction,
+// which the inference kernel runs on the matrix cores (one 32 x 32 quadrant
+// of the tile per wave, v_mfma_f32_32x32x8_bf16, fp32 accumulation); the
+// training kernels compute the same layer on the vector units from the same
+// bf16 activations.
 #include <math.h>
 
 #include "../../include/cbaa_mlp.h"
@@ -99,7 +106,8 @@ __device__ inline void tile_forward(const Net& n, Tile& t, uint32_t F, const flo
 #pragma unroll
     for (int f = 0; f < kMaxF; ++f)
       if (f < (int)F) z += n.W1[j * F + f] * xs[f];
-    t.a[lane][j] = z > 0.0f ? z : 0.0f;
+    // layer 2 reads h1 in bf16
+    t.a[lane][j] = bf16_to_f32(f32_to_bf16(z > 0.0f ? z : 0.0f));
   }
   __syncthreads();
   float part = 0.0f;
@@ -120,16 +128,86 @@ __device__ inline float tile_y(const Net& n, const Tile& t, uint32_t s) {
   return ((t.ypart[0][s] + t.ypart[1][s]) + (t.ypart[2][s] + t.ypart[3][s])) + n.b3;
 }
 
-__global__ __launch_bounds__(kThreads) void k_mlp_forward(uint32_t F, const float* master,
-                                                          const uint16_t* wbf, const float* x,
-                                                          uint64_t ns, float* y) {
-  __shared__ Net n;
-  __shared__ Tile t;
-  load_net(n, F, master, wbf);
+typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+// Inference with the second layer on the matrix cores. Per tile of 64
+// samples: layer 1 on the vector units (lane = sample, a quarter of the units
+// per wave), h1 stored in bf16; wave w computes the quadrant of z2 with
+// samples 32 (w / 2) .. and units 32 (w % 2) .. as eight 32 x 32 x 8 MFMAs
+// over the 64 inputs (A: h1 rows, B: W2 rows, both 4 consecutive bf16 per
+// lane); z2 + b2, relu, and the output layer's partial sums per quarter.
+__global__ __launch_bounds__(kThreads) void k_mlp_forward_mfma(uint32_t F, const float* master,
+                                                               const uint16_t* wbf,
+                                                               const float* x, uint64_t ns,
+                                                               float* y) {
+  __shared__ float W1[kH * kMaxF];
+  __shared__ float b1[kH], b2[kH], w3[kH];
+  __shared__ float b3;
+  __shared__ __align__(8) uint16_t W2[kH][kH + 4];   // bf16 rows (unit, input), padded
+  __shared__ __align__(8) uint16_t h1[kTile][kH + 4]; // bf16 (sample, unit), padded
+  __shared__ float xs[kTile][kMaxF];
+  __shared__ float h2[kTile][kH + 1];
+  __shared__ float ypart[4][kTile];
+  const Offsets o = offsets(F);
+  for (uint32_t i = threadIdx.x; i < kH * F; i += kThreads) W1[i] = bf16_to_f32(wbf[o.W1 + i]);
+  for (uint32_t i = threadIdx.x; i < kH * kH; i += kThreads) W2[i / kH][i % kH] = wbf[o.W2 + i];
+  for (uint32_t i = threadIdx.x; i < kH; i += kThreads) {
+    b1[i] = master[o.b1 + i];
+    b2[i] = master[o.b2 + i];
+    w3[i] = bf16_to_f32(wbf[o.w3 + i]);
+  }
+  if (threadIdx.x == 0) b3 = master[o.b3];
   __syncthreads();
+  const uint32_t lane = threadIdx.x % kWave;
+  const uint32_t q = threadIdx.x / kWave;
+  const uint32_t mi = q >> 1, ni = q & 1;          // this wave's quadrant
+  const uint32_t r = lane % 32, kq = (lane / 32) * 4;
   for (uint64_t s0 = (uint64_t)blockIdx.x * kTile; s0 < ns; s0 += (uint64_t)gridDim.x * kTile) {
-    tile_forward(n, t, F, x, s0, ns);
-    if (threadIdx.x < kTile && s0 + threadIdx.x < ns) y[s0 + threadIdx.x] = tile_y(n, t, threadIdx.x);
+    for (uint32_t i = threadIdx.x; i < kTile * F; i += kThreads) {
+      const uint32_t s = i / F, f = i % F;
+      xs[s][f] = s0 + s < ns ? x[(s0 + s) * F + f] : 0.0f;
+    }
+    __syncthreads();
+    // layer 1, in the same operation order as the training kernels
+    for (int jj = 0; jj < kH / 4; ++jj) {
+      const int j = q * (kH / 4) + jj;
+      float z = b1[j];
+      for (int f = 0; f < (int)F; ++f) z += W1[j * F + f] * xs[lane][f];
+      h1[lane][j] = f32_to_bf16(z > 0.0f ? z : 0.0f);
+    }
+    __syncthreads();
+    // layer 2 on the matrix cores
+    f32x16 acc;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) acc[v] = 0.0f;
+#pragma unroll
+    for (int kb = 0; kb < kH / 8; ++kb) {
+      const uint32_t k = kb * 8 + kq;
+      const bf16x4 a = *(const bf16x4*)&h1[mi * 32 + r][k];
+      const bf16x4 bv = *(const bf16x4*)&W2[ni * 32 + r][k];
+      acc = __builtin_amdgcn_mfma_f32_32x32x8bf16_1k(a, bv, acc, 0, 0, 0);
+    }
+    // lane holds z2[sample][unit] for unit ni*32 + r and samples
+    // mi*32 + (v % 4) + 4 (lane / 32) + 8 (v / 4), v < 16
+    const uint32_t unit = ni * 32 + r;
+#pragma unroll
+    for (int v = 0; v < 16; ++v) {
+      const uint32_t s = mi * 32 + (v % 4) + kq + 8 * (v / 4);
+      const float z = acc[v] + b2[unit];
+      h2[s][unit] = z > 0.0f ? z : 0.0f;
+    }
+    __syncthreads();
+    float part = 0.0f;
+    for (int kk = 0; kk < kH / 4; ++kk) {
+      const int k = q * (kH / 4) + kk;
+      part += w3[k] * h2[lane][k];
+    }
+    ypart[q][lane] = part;
+    __syncthreads();
+    if (threadIdx.x < kTile && s0 + threadIdx.x < ns)
+      y[s0 + threadIdx.x] = ((ypart[0][threadIdx.x] + ypart[1][threadIdx.x]) +
+                             (ypart[2][threadIdx.x] + ypart[3][threadIdx.x])) + b3;
     __syncthreads();
   }
 }
@@ -346,8 +424,8 @@ int cbaa_mlp_forward(uint32_t F, const float* d_master, const uint16_t* d_wbf, c
     set_error("null input or output");
     return CBAA_EINVAL;
   }
-  hipLaunchKernelGGL(k_mlp_forward, dim3(grid_tiles(n)), dim3(kThreads), 0, (hipStream_t)stream, F,
-                     d_master, d_wbf, d_x, n, d_y);
+  hipLaunchKernelGGL(k_mlp_forward_mfma, dim3(grid_tiles(n)), dim3(kThreads), 0,
+                     (hipStream_t)stream, F, d_master, d_wbf, d_x, n, d_y);
   return check("mlp forward launch");
 }
 

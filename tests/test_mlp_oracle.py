@@ -39,11 +39,44 @@ def test_gradient_matches_finite_differences(F):
     theta = rng.standard_normal(M.n_params(F)) * 0.3
     x = rng.uniform(0, 1, (40, F))
     t = rng.uniform(0, 8, 40)
-    loss, g = M.loss_and_grad(theta, F, x, t)
+    loss, g = M.loss_and_grad(theta, F, x, t, act_bf16=False)
     idx = rng.choice(M.n_params(F), 120, replace=False)
     fd = M.finite_difference_grad(theta, F, x, t, idx)
     assert np.allclose(g[idx], fd, rtol=1e-5, atol=1e-8)
     assert loss > 0
+
+
+def test_bf16_activations_of_the_second_layer():
+    """The device's definition of layer 2's inputs: z1 in fp32 (bias, then the
+    products in input order) agrees with fp64 to fp32 rounding; h1 enters z2
+    rounded to bf16, shown on a hand-built network whose output is h1[0]
+    itself: x = 1 + 2^-8 + 2^-10 gives z1 = x exactly in fp32, which rounds to
+    the bf16 value 1 + 2^-7; and the bf16-mode gradient stays within the
+    rounding of h1 of the fp64 network's."""
+    F = 1
+    theta = np.zeros(M.n_params(F))
+    W1, b1, W2, b2, w3, b3 = M.split(theta, F)   # views into theta
+    W1[:] = 1.0
+    W2[0, 0] = 1.0
+    w3[0] = 1.0
+    x = np.array([[1 + 2 ** -8 + 2 ** -10]], np.float32)
+    y_bf, _ = M.forward(theta, F, x)
+    y_ex, _ = M.forward(theta, F, x, act_bf16=False)
+    assert y_bf[0] == 1 + 2 ** -7
+    assert y_ex[0] == 1 + 2 ** -8 + 2 ** -10
+    rng = np.random.default_rng(9)
+    F = 6
+    theta = M.compute_params(rng.standard_normal(M.n_params(F)).astype(np.float32) * 0.3, F)
+    x = rng.uniform(0, 1, (300, F)).astype(np.float32)
+    z32 = M.layer1_fp32(theta, F, x).astype(np.float64)
+    W1, b1 = (a.astype(np.float64) for a in M.split(theta, F)[:2])
+    z64 = x.astype(np.float64) @ W1.T + b1
+    assert np.max(np.abs(z32 - z64)) <= 1e-6 * (np.max(np.abs(z64)) + 1)
+    t = rng.uniform(0, 8, 300)
+    _, g_bf = M.loss_and_grad(theta, F, x, t)
+    _, g_ex = M.loss_and_grad(theta, F, x, t, act_bf16=False)
+    assert np.max(np.abs(g_bf - g_ex)) <= 2 ** -7 * 4 * np.max(np.abs(g_ex))
+    assert not np.array_equal(g_bf, g_ex)
 
 
 def test_adam_matches_torch():
