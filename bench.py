@@ -842,8 +842,8 @@ def bench_serving(cfg, dev, args):
 
 def bench_learned(cfg, trace, g_src, local, dev, args):
     """The learned estimator trained on other windows and evaluated on this
-    one: three core-edge-shaped training windows of other seeds (32Mi packets
-    each, source-keyed cubes), at least 4M host rows drawn stratified by
+    one: three core-edge training windows of other seeds (the benchmark's
+    size, source-keyed cubes), at least 4M host rows drawn stratified by
     cardinality with exact counts; evaluation on up to 2M hosts of the
     benchmark's own window (its merged source-keyed cube), against the paper's
     linear count and the row-aware count at equal false-negative rate. Also
@@ -859,7 +859,7 @@ def bench_learned(cfg, trace, g_src, local, dev, args):
     xs, ts = [], []
     train_seeds = [args.seed + 101, args.seed + 102, args.seed + 103]
     for s in train_seeds:
-        tw = tracegen.window_core_edge(s, scale=0.5 * args.scale)
+        tw = tracegen.window_core_edge(s, scale=args.scale)
         cube = cbaa.new_cube(cfg, dev)
         nb = cbaa.cbaa_update_scratch_bytes(cfg, tw.n, 1)
         sc = cbaa.scratch_tensor(nb, dev)
@@ -908,7 +908,7 @@ def bench_learned(cfg, trace, g_src, local, dev, args):
         e1.synchronize()
     grad_ms = e0.elapsed_time(e1)
     mlp_fpr, row_fpr = rep["mlp"]["fpr"], rep["row"]["fpr"]
-    return {"train_windows": [f"core-edge seed {s}, 32Mi packets" for s in train_seeds],
+    return {"train_windows": [f"core-edge seed {s}, {int(64 * args.scale)}Mi packets" for s in train_seeds],
             "train_rows": int(x_tr.shape[0]), "test_rows": int(te.size),
             "test_window": f"the benchmark's window (seed {args.seed})",
             "epochs": tl.epochs, "features": int(x_tr.shape[1]),

@@ -230,7 +230,9 @@ typedef struct cbaa_stream_batch {
 #define CBAA_BATCH_FRESH 1
 
 /* Tile and partition shapes of the partitioned update (0 = library default):
- * chunk_pairs  pairs per histogram/scatter block (multiple of 1024, <= 2^22)
+ * chunk_pairs  pairs per piece of the sample that sizes the bins' regions
+ *              (every 64th piece of a stream is counted; multiple of 1024,
+ *              <= 2^22)
  * seg_records  records per apply work item (1024 .. 2^24)
  * apply_blocks persistent blocks of the apply step (1..65536) */
 typedef struct cbaa_tuning {
@@ -250,8 +252,9 @@ uint64_t cbaa_update_batch_scratch_bytes(const cbaa_config* h_cfg,
  * the same result as k cbaa_update (or cbaa_update2) calls (after zeroing
  * the cubes of streams flagged CBAA_BATCH_FRESH). Either every stream sets
  * d_cube_dst or none does. Streams without the flag may share cubes. The scratch
- * must hold the whole batch (CBAA_ESCRATCH otherwise); each stream's records
- * (pairs x cubes) must stay below 2^32. Only enqueues device work, so the
+ * must hold the whole batch (CBAA_ESCRATCH otherwise); a stream may have up to
+ * about 0.45 x 2^32 / cubes pairs (its records' regions and overflow list are
+ * addressed with 32-bit offsets; CBAA_EINVAL beyond). Only enqueues device work, so the
  * call can be captured into a HIP graph and replayed. Configurations outside
  * the partitioned path's limits (cbaa_update_scratch_bytes returns 0) get
  * CBAA_ECONFIG. */

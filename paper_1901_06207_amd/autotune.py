@@ -1,8 +1,8 @@
 """Autotuner for the partitioned update's tile/partition shapes.
 
 Times ``cbaa_update_batch`` on the caller's own streams with HIP events for a
-few shapes, one parameter at a time (coordinate descent over chunk size, apply
-segment size, apply grid), and returns the fastest. Results are cached per
+few shapes, one parameter at a time (coordinate descent over the sample's
+piece size, apply segment size, apply grid), and returns the fastest. Results are cached per
 (configuration, number of streams, total packets rounded to a power of two).
 """
 
@@ -14,7 +14,7 @@ import torch
 
 from . import cbaa
 
-CHUNKS = (16384, 32768, 65536, 131072)
+CHUNKS = (4096, 16384, 65536)
 SEGS = (32768, 65536, 131072)
 APPLY_BLOCKS = (256, 512, 1024)
 
@@ -58,7 +58,7 @@ def tune_update(cfg, streams, repeats: int = 3, use_cache: bool = True, stream=N
     need = max(cbaa.cbaa_update_batch_scratch_bytes(cfg, streams, dict(chunk_pairs=c))
                for c in CHUNKS)
     scratch = cbaa.scratch_tensor(need, streams[0][1].device)
-    best = dict(chunk_pairs=65536, seg_records=65536, apply_blocks=512)
+    best = dict(chunk_pairs=16384, seg_records=65536, apply_blocks=512)
     seen = {}
 
     def measure(t):

@@ -260,7 +260,7 @@ static int check_streams(const Dims& d, const cbaa_stream_batch* h, int k, Strea
     REQUIRE(nc == 2 || s.side == CBAA_SIDE_SRC || s.side == CBAA_SIDE_DST, "stream %d: bad side", i);
     REQUIRE(s.n_pairs == 0 || (s.d_pairs && ((uintptr_t)s.d_pairs & 7u) == 0),
             "stream %d: pairs null or misaligned", i);
-    REQUIRE((uint64_t)nc * s.n_pairs < 0xFFFFFFFFull, "stream %d: too many records", i);
+    REQUIRE(partitioned_stream_fits(d, s.n_pairs, nc), "stream %d: too many pairs", i);
     REQUIRE((s.flags & ~CBAA_BATCH_FRESH) == 0, "stream %d: unknown flags", i);
     if (s.flags & CBAA_BATCH_FRESH)
       for (int j = 0; j < k; ++j) {

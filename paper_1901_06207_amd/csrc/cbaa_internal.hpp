@@ -159,6 +159,8 @@ int launch_update_partitioned(const Dims& d, uint64_t* cube0, uint64_t* cube1,
                               const uint32_t* pairs, uint64_t n, int side, void* scratch,
                               uint64_t scratch_bytes, hipStream_t s);
 uint64_t partitioned_scratch_bytes(const Dims& d, uint64_t n_pairs, int n_cubes);
+// Whether one stream of n_pairs pairs fits the partitioned path's 32-bit record offsets.
+bool partitioned_stream_fits(const Dims& d, uint64_t n_pairs, int n_cubes);
 uint64_t partitioned_min_scratch_bytes(const Dims& d, int n_cubes, uint64_t n_pairs);
 bool partitioned_supported(const Dims& d);
 bool tuning_valid(const cbaa_tuning* t);

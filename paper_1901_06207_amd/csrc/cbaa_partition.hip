@@ -7,21 +7,24 @@
 //
 // The same launches serve one edge router's batch or K routers' batches of
 // uneven sizes at once (a stream table passed by value to every kernel):
-//   1. histogram   per chunk of pairs (chunks of all streams in one grid):
-//                  records per bin in LDS counters, added into the stream's
-//                  bin totals
-//   2. bases       per stream: exclusive prefixes over bins of records (a
-//                  bin's records are contiguous) and of apply segments; the
-//                  bins' write cursors start at their bases
-//   3. items       apply items prefixed over streams
-//   4. scatter     persistent blocks (one per CU, 768 threads) take scatter
+//   1. sample      every 64th piece (16 Ki pairs) of each stream: records per
+//                  bin in LDS counters, added into the stream's sampled counts
+//   2. bases       per stream: each bin's region (its sampled count scaled to
+//                  the stream, plus a margin for the sampling error) and the
+//                  prefix of the regions; the bins' write cursors start at
+//                  their bases. A bin's records are contiguous in its region.
+//   3. scatter     persistent blocks (one per CU, 768 threads) take scatter
 //                  chunks (20 pairs per thread), kept in registers, from a
-//                  shared counter; per
-//                  cube, rank the chunk's records inside their bins in LDS,
-//                  reserve each bin's run with one atomic add on its cursor,
-//                  stage the records bin-sorted and write every run
-//                  contiguously. The order of runs inside a bin is whatever
-//                  the atomics give: the OR of the bits does not depend on it
+//                  shared counter; per cube, rank the chunk's records inside
+//                  their bins in LDS, reserve each bin's run with one atomic
+//                  add on its cursor, stage the records bin-sorted and write
+//                  every run contiguously. The order of runs inside a bin is
+//                  whatever the atomics give: the OR of the bits does not
+//                  depend on it. Records past the end of a full region go to
+//                  the stream's overflow list instead
+//   4. fills       per stream: each region's fill and the exclusive prefix of
+//                  the apply segments; then the apply items prefixed over
+//                  streams
 //   5. apply       persistent blocks take (stream, bin, segment) items from a
 //                  shared counter (work stealing across streams): zero
 //                  an LDS tile, OR the records' bits into it, flush non-zero
@@ -29,7 +32,9 @@
 //                  stream whose cubes start empty and a bin with one item,
 //                  store the whole tile (the row block needs no zeroing)
 // Fresh streams' row blocks that no single item owns (empty bins and bins
-// split over several items) are zeroed before the apply.
+// split over several items) are zeroed before the apply. Last, the overflow
+// list of each stream (empty unless the sample misjudged a bin) is OR-ed into
+// its cubes with device-scope atomics, after every tile is in place.
 // A record is the mangled inner IP and the outer IP's bit with the cube index
 // in bit 31 (uint2); the apply step recomputes the columns from the mangled IP.
 #include "cbaa_internal.hpp"
@@ -45,21 +50,29 @@ constexpr int kApplyUnroll = 16;
 constexpr uint32_t kMaxTileWords = 16384; // 128 KiB LDS tile
 // Scatter blocks of 768 threads (12 waves) have 168 registers per lane: a
 // chunk of 20 pairs per thread stays in registers with no spill, and its
-// 8-byte records fill 120 KiB of LDS next to 12 KiB of counters for up to
-// 1024 bins per cube. Cubes of up to 4096 bins (e.g. 32 sketches, or
-// 8192-bit columns) take 18 pairs per thread beside 48 KiB of counters.
+// 8-byte records fill 120 KiB of LDS next to 24 KiB of per-bin counters, run
+// offsets and region ends for up to 1024 bins per cube. Cubes of up to 4096
+// bins (e.g. 32 sketches, or 8192-bit columns) take 14 pairs per thread
+// beside 64 KiB.
 constexpr int kScatterThreads = 768;
 constexpr uint32_t kSmallBins = 1024;     // bins per cube of the first shape
 constexpr int kScatterPerSmall = 20;
-constexpr int kScatterPerLarge = 18;
+constexpr int kScatterPerLarge = 14;
 inline uint32_t scatter_chunk(uint32_t per_cube) {
   return (per_cube <= kSmallBins ? kScatterPerSmall : kScatterPerLarge) * kScatterThreads;
 }
 constexpr uint32_t kScatterBlocks = 256;  // persistent scatter grid (one per CU)
-constexpr uint32_t kDefaultChunk = 65536;
+constexpr uint32_t kDefaultChunk = 16384;   // pairs per sampled piece
+constexpr uint32_t kSplit = 65536;          // a long update is split in multiples of this
 constexpr uint32_t kDefaultSeg = 65536;
 constexpr uint32_t kDefaultApplyBlocks = 512;
 constexpr uint32_t kNoRank = 0xFFFFu;
+// Every kSampleStride-th piece of a stream is counted, from its first; a
+// bin's region is its scaled sampled count e plus e/5 + 4 sqrt(e) + 64
+// records. At 16 Ki-pair pieces that is 1/64 of the pairs, spread evenly over
+// the stream, and ~500 sampled records per bin at the paper's dimensions: the
+// margin is several standard errors of the sample.
+constexpr uint32_t kSampleStride = 64;
 
 inline uint64_t align256(uint64_t x) { return (x + 255u) & ~uint64_t(255u); }
 
@@ -68,8 +81,10 @@ struct StreamDesc {
   uint64_t n;
   uint64_t* cube0;
   uint64_t* cube1;
-  uint64_t rec_base;      // first record of this stream
-  uint32_t chunk_begin;   // first global histogram chunk
+  uint64_t rec_base;      // first record of this stream's regions
+  uint32_t ovf_off;       // its overflow list, right after its regions
+  uint64_t sampled;       // pairs in its sampled pieces
+  uint32_t sample_begin;  // first global sampled piece
   uint32_t schunk_begin;  // first global scatter chunk
   uint32_t side;
   uint32_t fresh;         // cubes start empty: row blocks are stored, not OR-ed
@@ -78,22 +93,24 @@ struct StreamDesc {
 struct Batch {
   uint32_t k;
   uint32_t nbins;         // per stream: n_cubes * S * R
-  uint32_t total_chunks;  // histogram chunks of all streams
+  uint32_t total_samples; // sampled pieces of all streams
   uint32_t total_schunks; // scatter chunks of all streams
-  uint32_t chunk;         // pairs per histogram chunk
+  uint32_t chunk;         // pairs per piece
   uint32_t schunk;        // pairs per scatter chunk
   uint32_t seg;           // records per apply item
   StreamDesc s[CBAA_MAX_BATCH];
 };
 
 struct Layout {
-  uint32_t* tot;      // [k][nbins] records per bin (summed by the histogram)
+  uint32_t* tot;      // [k][nbins] sampled records per bin, later each region's fill
   uint32_t* next;     // [2] next apply item, next scatter chunk (right after tot)
+  uint32_t* ovfn;     // [k] entries of each stream's overflow list (right after next)
   uint32_t* cursor;   // [k][nbins] next free record of each bin (scatter)
   uint32_t* base;     // [k][nbins + 1] record offsets inside the stream
   uint32_t* segpre;   // [k][nbins + 1] apply items inside the stream
   uint32_t* items;    // [k + 1] apply items before each stream
-  uint2* rec;         // [sum of n_cubes * n]
+  uint2* rec;         // per stream: the bins' regions (region_records), then the
+                      // overflow list (n_cubes * n)
   uint64_t bytes;
 };
 
@@ -109,23 +126,55 @@ Tuning effective(const cbaa_tuning* t) {
   return r;
 }
 
+// Records the regions of a stream of n pairs can hold at most, whatever the
+// sample: the scaled sampled counts sum to n per cube, so the regions sum to
+// at most n_cubes n (1 + 1/5) + 4 sqrt(nbins n_cubes n) + 65 nbins (the last
+// term also absorbs the device's rounding of square roots).
+uint64_t region_records(uint64_t n, uint32_t n_cubes, uint32_t nbins) {
+  const uint64_t r = (uint64_t)n_cubes * n;
+  const uint64_t sq = (uint64_t)sqrt((double)nbins * (double)r) + 1;
+  return r + r / 5 + 4 * sq + 65ull * nbins;
+}
+
+// A stream's regions and its overflow list are addressed with 32-bit offsets,
+// and a bin's cursor may run past its region by the bin's whole count.
+bool fits(uint64_t n, uint32_t n_cubes, uint32_t nbins) {
+  return region_records(n, n_cubes, nbins) + (uint64_t)n_cubes * n < 0xFFFFFFFFull;
+}
+
+// Largest multiple of chunk that fits() (about 0.45 * 2^32 / n_cubes).
+uint64_t max_stream_pairs(const Dims& d, int n_cubes, uint64_t chunk) {
+  const uint32_t nbins = (uint32_t)n_cubes * d.S * d.R;
+  uint64_t lo = 0, hi = (0xFFFFFFFFull / (uint64_t)n_cubes) / chunk;   // in chunks
+  while (lo < hi) {
+    const uint64_t mid = (lo + hi + 1) / 2;
+    if (fits(mid * chunk, (uint32_t)n_cubes, nbins)) lo = mid; else hi = mid - 1;
+  }
+  return lo * chunk;
+}
+
 // Fills the batch's chunk and record bookkeeping and carves the scratch.
 Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
   b.nbins = (uint32_t)n_cubes * d.S * d.R;
   b.chunk = chunk;
   b.schunk = scatter_chunk(d.S * d.R);
-  uint32_t ch = 0, sch = 0;
+  uint32_t sp = 0, sch = 0;
   uint64_t rec = 0;
   for (uint32_t i = 0; i < b.k; ++i) {
     StreamDesc& s = b.s[i];
-    s.chunk_begin = ch;
+    s.sample_begin = sp;
     s.schunk_begin = sch;
     s.rec_base = rec;
-    ch += (uint32_t)((s.n + chunk - 1) / chunk);
+    const uint64_t nch = (s.n + chunk - 1) / chunk;
+    s.sampled = 0;
+    for (uint64_t c = 0; c < nch; c += kSampleStride)
+      s.sampled += s.n - c * chunk < chunk ? s.n - c * chunk : chunk;
+    sp += (uint32_t)((nch + kSampleStride - 1) / kSampleStride);
     sch += (uint32_t)((s.n + b.schunk - 1) / b.schunk);
-    rec += (uint64_t)n_cubes * s.n;
+    s.ovf_off = s.n ? (uint32_t)region_records(s.n, (uint32_t)n_cubes, b.nbins) : 0u;
+    rec += s.ovf_off + (uint64_t)n_cubes * s.n;
   }
-  b.total_chunks = ch;
+  b.total_samples = sp;
   b.total_schunks = sch;
   Layout L;
   uint64_t off = 0;
@@ -135,8 +184,9 @@ Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
     off += align256(bytes);
     return (void*)q;
   };
-  L.tot = (uint32_t*)take(((uint64_t)b.k * b.nbins + 2) * 4);
+  L.tot = (uint32_t*)take(((uint64_t)b.k * b.nbins + 2 + b.k) * 4);
   L.next = L.tot + (uint64_t)b.k * b.nbins;
+  L.ovfn = L.next + 2;
   L.cursor = (uint32_t*)take((uint64_t)b.k * b.nbins * 4);
   L.base = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
   L.segpre = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
@@ -146,13 +196,13 @@ Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
   return L;
 }
 
-// Stream owning global chunk x: the last stream whose first chunk is <= x
-// (streams without chunks share their successor's start and are skipped by
-// taking the last match).
-__device__ inline uint32_t owner_of_chunk(const Batch& b, uint32_t x) {
+// Stream owning global sampled piece x: the last stream whose first piece is
+// <= x (streams without pairs share their successor's start and are skipped
+// by taking the last match).
+__device__ inline uint32_t owner_of_sample(const Batch& b, uint32_t x) {
   uint32_t s = 0;
   for (uint32_t i = 1; i < b.k; ++i)
-    if (b.s[i].chunk_begin <= x) s = i;
+    if (b.s[i].sample_begin <= x) s = i;
   return s;
 }
 
@@ -197,12 +247,12 @@ __global__ void k_begin(Dims d, Batch b, uint32_t* p, uint32_t n) {
 template <bool TWO>
 __global__ __launch_bounds__(kBlock) void k_histogram(Dims d, Batch b, uint32_t* tot) {
   __shared__ uint32_t hist[kMaxBins];
-  const uint32_t gc = blockIdx.x;
-  const uint32_t si = owner_of_chunk(b, gc);
+  const uint32_t gs = blockIdx.x;
+  const uint32_t si = owner_of_sample(b, gs);
   const StreamDesc& st = b.s[si];
   for (uint32_t i = threadIdx.x; i < b.nbins; i += kBlock) hist[i] = 0;
   __syncthreads();
-  const uint64_t lo = (uint64_t)(gc - st.chunk_begin) * b.chunk;
+  const uint64_t lo = (uint64_t)(gs - st.sample_begin) * kSampleStride * b.chunk;
   const uint64_t hi = lo + b.chunk < st.n ? lo + b.chunk : st.n;
   const int side = st.side;
   for (uint64_t k0 = lo + threadIdx.x; k0 < hi; k0 += (uint64_t)kBlock * kUnroll) {
@@ -254,47 +304,75 @@ __device__ inline uint32_t block_exclusive_scan(uint32_t v, uint32_t* lds_waves,
   return before + incl - v;
 }
 
-// Block si: exclusive prefixes over stream si's bins of records (base, also
-// the scatter's starting cursors) and of apply segments (segpre).
+// Block si: each bin's region, from its sampled count e scaled to the stream
+// (e = sampled * n / pairs sampled): e + e/5 + 4 sqrt(e) + 64 records, and
+// the exclusive prefix of the regions (base, also the scatter's starting
+// cursors).
 __global__ __launch_bounds__(kBlock) void k_bases(Batch b, const uint32_t* __restrict__ tot,
-                                                  uint32_t* base, uint32_t* segpre,
-                                                  uint32_t* cursor) {
+                                                  uint32_t* base, uint32_t* cursor) {
   __shared__ uint32_t waves[kBlock / kWave];
-  __shared__ uint32_t carry_rec, carry_seg;
+  __shared__ uint32_t carry;
   const uint32_t si = blockIdx.x;
+  const StreamDesc& st = b.s[si];
   const uint32_t* t = tot + (uint64_t)si * b.nbins;
   uint32_t* bs = base + (uint64_t)si * (b.nbins + 1);
-  uint32_t* sp = segpre + (uint64_t)si * (b.nbins + 1);
   uint32_t* cu = cursor + (uint64_t)si * b.nbins;
-  if (threadIdx.x == 0) {
-    carry_rec = 0;
-    carry_seg = 0;
-  }
+  if (threadIdx.x == 0) carry = 0;
   __syncthreads();
   for (uint32_t b0 = 0; b0 < b.nbins; b0 += kBlock) {
     const uint32_t bin = b0 + threadIdx.x;
-    const uint32_t n = bin < b.nbins ? t[bin] : 0u;
-    const uint32_t nseg = (n + b.seg - 1) / b.seg;
-    uint32_t sum_rec, sum_seg;
-    const uint32_t ex_rec = block_exclusive_scan(n, waves, sum_rec);
-    const uint32_t ex_seg = block_exclusive_scan(nseg, waves, sum_seg);
-    const uint32_t cr = carry_rec, cg = carry_seg;
+    uint32_t cap = 0;
+    if (bin < b.nbins && st.n) {
+      const uint64_t e = (uint64_t)t[bin] * st.n / st.sampled;
+      cap = (uint32_t)(e + e / 5 + 4 * (uint64_t)sqrtf((float)e) + 64);
+    }
+    uint32_t sum;
+    const uint32_t ex = block_exclusive_scan(cap, waves, sum);
+    const uint32_t cr = carry;
     if (bin < b.nbins) {
-      bs[bin] = cr + ex_rec;
-      cu[bin] = cr + ex_rec;
-      sp[bin] = cg + ex_seg;
+      bs[bin] = cr + ex;
+      cu[bin] = cr + ex;
     }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      carry_rec = cr + sum_rec;
-      carry_seg = cg + sum_seg;
-    }
+    if (threadIdx.x == 0) carry = cr + sum;
     __syncthreads();
   }
-  if (threadIdx.x == 0) {
-    bs[b.nbins] = carry_rec;
-    sp[b.nbins] = carry_seg;
+  if (threadIdx.x == 0) bs[b.nbins] = carry;
+}
+
+// Block si, after the scatter: each region's fill (its cursor, capped at the
+// region's end; the rest went to the overflow list), kept in tot, and the
+// exclusive prefix of the apply segments the fills need (segpre).
+__global__ __launch_bounds__(kBlock) void k_fills(Batch b, const uint32_t* __restrict__ base,
+                                                  const uint32_t* __restrict__ cursor,
+                                                  uint32_t* tot, uint32_t* segpre) {
+  __shared__ uint32_t waves[kBlock / kWave];
+  __shared__ uint32_t carry;
+  const uint32_t si = blockIdx.x;
+  const uint32_t* bs = base + (uint64_t)si * (b.nbins + 1);
+  const uint32_t* cu = cursor + (uint64_t)si * b.nbins;
+  uint32_t* t = tot + (uint64_t)si * b.nbins;
+  uint32_t* sp = segpre + (uint64_t)si * (b.nbins + 1);
+  if (threadIdx.x == 0) carry = 0;
+  __syncthreads();
+  for (uint32_t b0 = 0; b0 < b.nbins; b0 += kBlock) {
+    const uint32_t bin = b0 + threadIdx.x;
+    uint32_t nseg = 0;
+    if (bin < b.nbins) {
+      const uint32_t end = bs[bin + 1], c = cu[bin];
+      const uint32_t fill = (c < end ? c : end) - bs[bin];
+      t[bin] = fill;
+      nseg = (uint32_t)(((uint64_t)fill + b.seg - 1) / b.seg);
+    }
+    uint32_t sum;
+    const uint32_t ex = block_exclusive_scan(nseg, waves, sum);
+    const uint32_t cr = carry;
+    if (bin < b.nbins) sp[bin] = cr + ex;
+    __syncthreads();
+    if (threadIdx.x == 0) carry = cr + sum;
+    __syncthreads();
   }
+  if (threadIdx.x == 0) sp[b.nbins] = carry;
 }
 
 __global__ void k_stream_items(Batch b, const uint32_t* segpre, uint32_t* items) {
@@ -316,15 +394,31 @@ __device__ inline uint32_t unpack_rank(uint32_t rk, int u) { return (rk >> (16 *
 // NB: the most bins per cube the LDS counters hold; PER: pairs per thread.
 template <bool TWO, uint32_t NB, int PER>
 __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, uint32_t* cursor,
-                                                    uint2* __restrict__ rec_all, uint32_t* ctr) {
+                                                    const uint32_t* __restrict__ base,
+                                                    uint2* __restrict__ rec_all,
+                                                    uint32_t* ovfn,
+                                                    uint32_t* ctr) {
   __shared__ uint32_t s_next;
+  __shared__ uint32_t s_over;   // some bin of this chunk and cube overflows
   constexpr int kPer = PER;
   constexpr uint32_t P = PER * kScatterThreads;
-  __shared__ uint2 stage[P];
-  __shared__ uint32_t cnt[NB];
-  __shared__ uint32_t start[NB];
-  __shared__ uint32_t gpos[NB];
-  __shared__ uint32_t waves[kScatterThreads / kWave];
+  // One LDS block, per-bin arrays first: a thread's bins in all of them are
+  // one address register plus offsets the LDS instructions encode (< 64 KiB).
+  // The first shape also keeps its stream's region ends here (8 KiB); the
+  // second reads them with the cursor adds.
+  constexpr bool kEndsInLds = NB <= kSmallBins;
+  constexpr uint32_t kEndsWords = kEndsInLds ? 2 * NB : 0;
+  constexpr uint32_t kStageWord = 4 * NB + kEndsWords + kScatterThreads / kWave;
+  static_assert(kStageWord % 2 == 0, "stage must be 8-byte aligned");
+  __shared__ __align__(16) uint32_t lds[kStageWord + 2 * P];
+  uint32_t* cnt = lds;              // counts, then the end of the run's in-region part
+  uint32_t* start = lds + NB;       // first stage slot of each bin's run
+  uint32_t* din = lds + 2 * NB;     // region position of a stage slot, minus the slot
+  uint32_t* dov = lds + 3 * NB;     // overflow position of a stage slot, minus the slot
+  uint32_t* ends = lds + 4 * NB;    // region ends of both cubes (first shape)
+  uint32_t* waves = lds + 4 * NB + kEndsWords;
+  uint2* stage = (uint2*)(lds + kStageWord);
+  uint32_t ends_of = 0xFFFFFFFFu;   // stream whose ends are in LDS
   // bins per thread in the count scan
   constexpr uint32_t kNpt = (NB + kScatterThreads - 1) / kScatterThreads;
   const uint32_t per_cube = d.S * d.R;   // bins of one cube (<= NB)
@@ -334,10 +428,14 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, ui
     const uint64_t lo = (uint64_t)(gc - st.schunk_begin) * P;
     const uint32_t rem = st.n - lo < P ? (uint32_t)(st.n - lo) : P;
     const uint2* src = st.pairs + lo;
+    // held as (inner, outer) of the first cube: a destination-keyed
+    // one-cube stream swaps its pairs on load
+    const bool swap = !TWO && st.side != CBAA_SIDE_SRC;
 #pragma unroll
     for (int u = 0; u < kPer; ++u) {
       const uint32_t k = threadIdx.x + u * kScatterThreads;
-      p[u] = k < rem ? src[k] : make_uint2(0u, 0u);
+      const uint2 v = k < rem ? src[k] : make_uint2(0u, 0u);
+      p[u] = swap ? make_uint2(v.y, v.x) : v;
     }
   };
   // chunks are taken from a shared counter (work stealing); the next one is
@@ -354,20 +452,25 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, ui
     const StreamDesc& st = b.s[si];
     uint2* rec = rec_all + st.rec_base;
     uint32_t* cur = cursor + (uint64_t)si * b.nbins;
+    const uint32_t* bend = base + (uint64_t)si * (b.nbins + 1) + 1;   // region ends
     const uint64_t lo = (uint64_t)(gc - st.schunk_begin) * P;
     const uint32_t rem = st.n - lo < P ? (uint32_t)(st.n - lo) : P;
-    const int side = st.side;
+    if (kEndsInLds && si != ends_of) {   // uniform: si is the block's
+      for (uint32_t i = threadIdx.x; i < b.nbins; i += kScatterThreads) ends[i] = bend[i];
+      ends_of = si;
+    }
 #pragma unroll
     for (int k = 0; k < (TWO ? 2 : 1); ++k) {
       for (uint32_t i = threadIdx.x; i < per_cube; i += kScatterThreads) cnt[i] = 0;
+      if (threadIdx.x == 0) s_over = 0;
       __syncthreads();
       uint32_t rk[(kPer + 1) / 2];
 #pragma unroll
       for (int u = 0; u < (kPer + 1) / 2; ++u) rk[u] = 0;
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
-        const uint32_t h0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].x : p[u].y) : p[u].y;
-        const uint32_t p0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].y : p[u].x) : p[u].x;
+        const uint32_t h0 = k == 0 ? p[u].x : p[u].y;
+        const uint32_t p0 = k == 0 ? p[u].y : p[u].x;
         uint2 r;
         const uint32_t bl = bin_of(d, k, h0, p0, r) - k * per_cube;
         const uint32_t rank = threadIdx.x + u * kScatterThreads < rem ? atomicAdd(&cnt[bl], 1u) : kNoRank;
@@ -376,39 +479,58 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, ui
       __syncthreads();
       // local runs (exclusive prefix of the counts, kNpt consecutive bins per
       // thread) and global runs (one atomic add per non-empty bin on the
-      // stream's cursor; a thread's adds are in flight together)
-      uint32_t c[kNpt], g[kNpt], sum = 0;
+      // stream's cursor; a thread's adds are in flight together). The part
+      // of a run past its region's end goes to the overflow list.
+      // (the counts are read from LDS again rather than held in registers)
+      uint32_t g[kNpt], e[kNpt], sum = 0;
 #pragma unroll
       for (uint32_t j = 0; j < kNpt; ++j) {
         const uint32_t i = threadIdx.x * kNpt + j;
-        c[j] = i < per_cube ? cnt[i] : 0u;
-        sum += c[j];
-      }
-#pragma unroll
-      for (uint32_t j = 0; j < kNpt; ++j) {
-        const uint32_t i = threadIdx.x * kNpt + j;
-        g[j] = c[j] ? __hip_atomic_fetch_add(cur + k * per_cube + i, c[j], __ATOMIC_RELAXED,
-                                             __HIP_MEMORY_SCOPE_AGENT)
-                    : 0u;
+        const uint32_t c = i < per_cube ? cnt[i] : 0u;
+        sum += c;
+        g[j] = c ? __hip_atomic_fetch_add(cur + k * per_cube + i, c, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT)
+                 : 0u;
+        if (!kEndsInLds) e[j] = c ? bend[k * per_cube + i] : 0u;
       }
       uint32_t total;
       uint32_t run = block_exclusive_scan<kScatterThreads>(sum, waves, total);
 #pragma unroll
       for (uint32_t j = 0; j < kNpt; ++j) {
         const uint32_t i = threadIdx.x * kNpt + j;
+        const uint32_t c = i < per_cube ? cnt[i] : 0u;
         if (i < per_cube) {
+          const uint32_t ej = kEndsInLds ? ends[k * per_cube + i] : e[j];
+          const uint32_t room = g[j] < ej ? ej - g[j] : 0u;
+          const uint32_t nin = c < room ? c : room;
           start[i] = run;
-          gpos[i] = g[j];
+          cnt[i] = run + nin;
+          din[i] = g[j] - run;
+          dov[i] = c - nin;   // records past the region's end, placed below
+          if (c != nin) s_over = 1;
         }
-        run += c[j];
+        run += c;
       }
       __syncthreads();
+      if (s_over) {   // uniform; rare: the sample gave some bin too little room
+#pragma unroll
+        for (uint32_t j = 0; j < kNpt; ++j) {
+          const uint32_t i = threadIdx.x * kNpt + j;
+          const uint32_t nov = i < per_cube ? dov[i] : 0u;
+          if (nov) {
+            const uint32_t ob = __hip_atomic_fetch_add(ovfn + si, nov, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_AGENT);
+            dov[i] = st.ovf_off + ob - cnt[i];
+          }
+        }
+        __syncthreads();
+      }
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
         const uint32_t rank = unpack_rank(rk[u / 2], u);
         if (rank == kNoRank) continue;
-        const uint32_t h0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].x : p[u].y) : p[u].y;
-        const uint32_t p0 = k == 0 ? (side == CBAA_SIDE_SRC ? p[u].y : p[u].x) : p[u].x;
+        const uint32_t h0 = k == 0 ? p[u].x : p[u].y;
+        const uint32_t p0 = k == 0 ? p[u].y : p[u].x;
         uint2 r;
         const uint32_t bl = bin_of(d, k, h0, p0, r) - k * per_cube;
         stage[start[bl] + rank] = r;
@@ -420,10 +542,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, ui
         gc_cur = s_next;
         if (gc_cur < b.total_schunks) load(gc_cur);
       }
+      const bool over = s_over != 0;   // uniform
       for (uint32_t t = threadIdx.x; t < total; t += kScatterThreads) {
         const uint2 v = stage[t];
         const uint32_t bl = bin_of_record(d, v) - k * per_cube;
-        rec[gpos[bl] + (t - start[bl])] = v;
+        rec[(over && t >= cnt[bl] ? dov[bl] : din[bl]) + t] = v;
       }
       __syncthreads();
     }
@@ -460,6 +583,7 @@ __device__ inline uint32_t upper_index(const uint32_t* tab, uint32_t n, uint32_t
 template <int NRA, int NVA>
 __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* __restrict__ rec_all,
                                                   const uint32_t* __restrict__ base,
+                                                  const uint32_t* __restrict__ fill,
                                                   const uint32_t* __restrict__ segpre,
                                                   const uint32_t* __restrict__ items,
                                                   uint32_t* next) {
@@ -482,8 +606,10 @@ __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* 
     const uint32_t local = item - items[si];
     const uint32_t bin = upper_index(sp, b.nbins, local);
     const uint32_t seg = local - sp[bin];
-    const uint32_t r0 = bs[bin] + seg * b.seg;
-    const uint32_t r1 = r0 + b.seg < bs[bin + 1] ? r0 + b.seg : bs[bin + 1];
+    const uint64_t r0w = (uint64_t)bs[bin] + (uint64_t)seg * b.seg;
+    const uint64_t end = (uint64_t)bs[bin] + fill[(uint64_t)si * b.nbins + bin];
+    const uint32_t r0 = (uint32_t)r0w;
+    const uint32_t r1 = (uint32_t)(r0w + b.seg < end ? r0w + b.seg : end);
     const uint2* rec = rec_all + st.rec_base;
     for (uint32_t w = threadIdx.x; w < d.W; w += kBlock) tile[w] = 0;
     __syncthreads();
@@ -532,6 +658,35 @@ __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* 
   }
 }
 
+// The records no region could take: each is OR-ed into its cube with A
+// device-scope atomics (Alg. 1 as the direct path does it), after the apply
+// has put every tile in place. Block (part, stream); nothing to do in the
+// usual case.
+template <int NRA, int NVA>
+__global__ __launch_bounds__(256) void k_overflow(Dims d, Batch b, const uint2* __restrict__ rec_all,
+                                                  const uint32_t* __restrict__ ovfn) {
+  const uint32_t si = blockIdx.y;
+  const StreamDesc& st = b.s[si];
+  const uint32_t n = ovfn[si];
+  const uint2* o = rec_all + st.rec_base + st.ovf_off;
+  for (uint32_t i = blockIdx.x * 256 + threadIdx.x; i < n; i += gridDim.x * 256) {
+    const uint2 r = o[i];
+    const uint32_t row = r.y & 0x7FFFFFFFu;
+    uint64_t* cube = (r.y >> 31) ? st.cube1 : st.cube0;
+    const uint32_t cs = r.x & low_mask(d.r), lp = r.x >> d.r;
+    uint64_t* blk = cube + ((uint64_t)cs * d.R + (row >> 6)) * d.W;
+    const uint64_t bit = 1ull << (row & 63u);
+#pragma unroll
+    for (int a = 0; a < NRA; ++a)
+      __hip_atomic_fetch_or(blk + d.aoff[a] + (rotr_in(lp, d.off[a], d.L) & low_mask(d.cbn[a])), bit,
+                            __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+#pragma unroll
+    for (int j = 0; j < NVA; ++j)
+      __hip_atomic_fetch_or(blk + d.aoff[NRA + j] + va_col(d, j, lp), bit, __ATOMIC_RELAXED,
+                            __HIP_MEMORY_SCOPE_AGENT);
+  }
+}
+
 int check(const char* what) {
   hipError_t e = hipGetLastError();
   return e == hipSuccess ? CBAA_OK : hip_fail(e, what);
@@ -540,8 +695,11 @@ int check(const char* what) {
 template <int NRA, int NVA>
 int apply_dispatch(const Dims& d, const Batch& b, const Layout& L, uint32_t blocks, hipStream_t s) {
   hipLaunchKernelGGL((k_apply<NRA, NVA>), dim3(blocks), dim3(kBlock), 0, s, d, b, L.rec, L.base,
-                     L.segpre, L.items, L.next);
-  return check("apply launch");
+                     L.tot, L.segpre, L.items, L.next);
+  int rc = check("apply launch");
+  if (rc != CBAA_OK) return rc;
+  hipLaunchKernelGGL((k_overflow<NRA, NVA>), dim3(256, b.k), dim3(256), 0, s, d, b, L.rec, L.ovfn);
+  return check("overflow launch");
 }
 
 int run_apply(const Dims& d, const Batch& b, const Layout& L, uint32_t blocks, hipStream_t s) {
@@ -559,10 +717,11 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
   int rc;
   bool any_fresh = false;
   for (uint32_t i = 0; i < b.k; ++i) any_fresh = any_fresh || b.s[i].fresh;
-  const uint32_t nt = b.k * b.nbins + 2;   // bin totals, the apply's and the scatter's counters
+  // sampled counts, the apply's and the scatter's counters, overflow counts
+  const uint32_t nt = b.k * b.nbins + 2 + b.k;
   hipLaunchKernelGGL(k_begin, dim3((nt + 255) / 256), dim3(256), 0, s, d, b, L.tot, nt);
   if ((rc = check("begin launch")) != CBAA_OK) return rc;
-  if (b.total_chunks == 0) {   // no pairs at all: fresh cubes are just emptied
+  if (b.total_samples == 0) {   // no pairs at all: fresh cubes are just emptied
     for (uint32_t i = 0; i < b.k && any_fresh; ++i) {
       if (!b.s[i].fresh) continue;
       if ((rc = launch_fill_zero(b.s[i].cube0, d.words, s)) != CBAA_OK) return rc;
@@ -570,24 +729,28 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
     }
     return CBAA_OK;
   }
-  hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_chunks), dim3(kBlock), 0, s, d, b, L.tot);
+  hipLaunchKernelGGL((k_histogram<TWO>), dim3(b.total_samples), dim3(kBlock), 0, s, d, b, L.tot);
   if ((rc = check("histogram launch")) != CBAA_OK) return rc;
-  hipLaunchKernelGGL(k_bases, dim3(b.k), dim3(kBlock), 0, s, b, L.tot, L.base, L.segpre, L.cursor);
+  hipLaunchKernelGGL(k_bases, dim3(b.k), dim3(kBlock), 0, s, b, L.tot, L.base, L.cursor);
   if ((rc = check("bases launch")) != CBAA_OK) return rc;
+  const uint32_t sgrid = b.total_schunks < kScatterBlocks ? b.total_schunks : kScatterBlocks;
+  if (d.S * d.R <= kSmallBins)
+    hipLaunchKernelGGL((k_scatter<TWO, kSmallBins, kScatterPerSmall>), dim3(sgrid),
+                       dim3(kScatterThreads), 0, s, d, b, L.cursor, L.base, L.rec, L.ovfn,
+                       L.next + 1);
+  else
+    hipLaunchKernelGGL((k_scatter<TWO, kMaxBins / 2, kScatterPerLarge>), dim3(sgrid),
+                       dim3(kScatterThreads), 0, s, d, b, L.cursor, L.base, L.rec, L.ovfn,
+                       L.next + 1);
+  if ((rc = check("scatter launch")) != CBAA_OK) return rc;
+  hipLaunchKernelGGL(k_fills, dim3(b.k), dim3(kBlock), 0, s, b, L.base, L.cursor, L.tot, L.segpre);
+  if ((rc = check("fills launch")) != CBAA_OK) return rc;
   hipLaunchKernelGGL(k_stream_items, dim3(1), dim3(64), 0, s, b, L.segpre, L.items);
   if ((rc = check("items launch")) != CBAA_OK) return rc;
   if (any_fresh) {
     hipLaunchKernelGGL(k_clear_fresh, dim3(b.nbins, b.k), dim3(256), 0, s, d, b, L.segpre);
     if ((rc = check("clear launch")) != CBAA_OK) return rc;
   }
-  const uint32_t sgrid = b.total_schunks < kScatterBlocks ? b.total_schunks : kScatterBlocks;
-  if (d.S * d.R <= kSmallBins)
-    hipLaunchKernelGGL((k_scatter<TWO, kSmallBins, kScatterPerSmall>), dim3(sgrid),
-                       dim3(kScatterThreads), 0, s, d, b, L.cursor, L.rec, L.next + 1);
-  else
-    hipLaunchKernelGGL((k_scatter<TWO, kMaxBins / 2, kScatterPerLarge>), dim3(sgrid),
-                       dim3(kScatterThreads), 0, s, d, b, L.cursor, L.rec, L.next + 1);
-  if ((rc = check("scatter launch")) != CBAA_OK) return rc;
   return run_apply(d, b, L, apply_blocks, s);
 }
 
@@ -634,17 +797,21 @@ int launch_update_batch(const Dims& d, const StreamSpec* specs, int k, int n_cub
                       : run<false>(d, b, L, tu.apply_blocks, s);
 }
 
+bool partitioned_stream_fits(const Dims& d, uint64_t n_pairs, int n_cubes) {
+  return fits(n_pairs, (uint32_t)n_cubes, (uint32_t)n_cubes * d.S * d.R);
+}
+
 uint64_t partitioned_scratch_bytes(const Dims& d, uint64_t n_pairs, int n_cubes) {
   StreamSpec sp{};
   const uint64_t nb = n_pairs == 0 ? 1 : n_pairs;
-  const uint64_t cap = (0xFFFFFFFFull / (uint64_t)n_cubes) / kDefaultChunk * kDefaultChunk;
+  const uint64_t cap = max_stream_pairs(d, n_cubes, kSplit);
   sp.n = nb > cap ? cap : nb;
   return batch_scratch_bytes(d, &sp, 1, n_cubes, nullptr);
 }
 
 uint64_t partitioned_min_scratch_bytes(const Dims& d, int n_cubes, uint64_t n_pairs) {
   StreamSpec sp{};
-  sp.n = n_pairs < kDefaultChunk ? n_pairs : kDefaultChunk;
+  sp.n = n_pairs < kSplit ? n_pairs : kSplit;
   return batch_scratch_bytes(d, &sp, 1, n_cubes, nullptr);
 }
 
@@ -652,10 +819,9 @@ int launch_update_partitioned(const Dims& d, uint64_t* c0, uint64_t* c1, const u
                               uint64_t n, int side, void* scratch, uint64_t scratch_bytes,
                               hipStream_t s) {
   const int nc = c1 ? 2 : 1;
-  const uint64_t chunk = kDefaultChunk;
-  // largest batch (whole chunks) that fits the scratch; a stream's records are
-  // addressed with 32-bit offsets
-  const uint64_t cap = (0xFFFFFFFFull / (uint64_t)nc) / chunk * chunk;
+  const uint64_t chunk = kSplit;
+  // largest batch (whole chunks) that fits the scratch and 32-bit offsets
+  const uint64_t cap = max_stream_pairs(d, nc, chunk);
   auto bytes_for = [&](uint64_t m) {
     StreamSpec sp{};
     sp.n = m;

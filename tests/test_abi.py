@@ -137,6 +137,31 @@ def test_tuning_bounds():
                                  None) == cbaa.CBAA_EINVAL
 
 
+def test_batch_stream_size_limit():
+    """A stream's regions (its sampled room, about 1.2x its records) and its
+    overflow list (room for every record) are addressed with 32-bit offsets:
+    about 0.45 x 2^32 / cubes pairs fit, 2^30 pairs with two cubes do not;
+    the refusal happens on the host."""
+    import ctypes as C
+    from paper_1901_06207_amd import cbaa
+    lib = cbaa.lib()
+    c = cbaa.Config().to_c()
+    table = (cbaa.cbaa_stream_batch * 1)()
+    table[0].d_pairs, table[0].d_cube, table[0].d_cube_dst = 16, 256, 4096
+    table[0].n_pairs = 900_000_000
+    assert lib.cbaa_update_batch_scratch_bytes(C.byref(c), table, 1, None) > 0
+    table[0].n_pairs = 1 << 30
+    assert lib.cbaa_update_batch_scratch_bytes(C.byref(c), table, 1, None) == 0
+    assert lib.cbaa_update_batch(C.byref(c), table, 1, None, 256, 1 << 40,
+                                 None) == cbaa.CBAA_EINVAL
+    assert "too many pairs" in cbaa.cbaa_last_error()
+    table[0].d_cube_dst = None
+    table[0].n_pairs = 1_800_000_000
+    assert lib.cbaa_update_batch_scratch_bytes(C.byref(c), table, 1, None) > 0
+    table[0].n_pairs = 1 << 31
+    assert lib.cbaa_update_batch_scratch_bytes(C.byref(c), table, 1, None) == 0
+
+
 def _fnv1a64_words(words):
     """64-bit FNV-1a over the little-endian bytes of 32-bit words."""
     h = 0xCBF29CE484222325

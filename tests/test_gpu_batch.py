@@ -299,7 +299,7 @@ def test_batch_of_32_streams_with_a_64mi_stream(cb):
                                   dict(r=5, cl_bs=[5, 14, 23], log2_g=13)])
 def test_batch_with_up_to_4096_bins_per_cube(cb, dims):
     """Cubes of 2048 and 4096 bins per cube (32 sketches, 8192-bit columns,
-    both) take the partitioned path's second shape (18 pairs per thread
+    both) take the partitioned path's second shape (14 pairs per thread
     beside larger LDS counters): both cubes of uneven streams, fresh and
     OR-ing, bit-exact against the oracle."""
     import torch
@@ -322,3 +322,53 @@ def test_batch_with_up_to_4096_bins_per_cube(cb, dims):
         src = np.concatenate([parts[0], q]) if i == 3 else q
         assert np.array_equal(cb.cube_to_numpy(a), O.cube_of(p, src, 0)), i
         assert np.array_equal(cb.cube_to_numpy(b), O.cube_of(p, src, 1)), i
+
+
+def _skewed_stream(seed):
+    """Three histogram chunks of 65536 pairs: random pairs, then one host
+    with 65536 distinct destinations, then one destination with 65536
+    distinct sources. Only the first chunk is sampled, where every bin (one
+    row block of one sketch) gets about 64 records; the two hosts' sketches
+    get about 1024 records in each of their 64 row blocks' bins, several
+    times the room the sample gives them."""
+    rng = np.random.default_rng(seed)
+    n = 65536
+    rand = rng.integers(0, 1 << 32, (n, 2), dtype=np.uint64).astype(np.uint32)
+    peers = rng.choice(1 << 32, 2 * n, replace=False).astype(np.uint32)
+    out = np.column_stack([np.full(n, 0x0A000001, np.uint32), peers[:n]])
+    inn = np.column_stack([peers[n:], np.full(n, 0xC0A80101, np.uint32)])
+    return np.concatenate([rand, out, inn])
+
+
+@pytest.mark.parametrize("two", [False, True])
+def test_bins_the_sample_underestimates_overflow_exactly(cb, two):
+    """Records beyond a bin's sampled room take the overflow list and are
+    OR-ed in after the apply: fresh and OR-ing streams, one and two cubes,
+    bit-exact against the oracle."""
+    import torch
+    p = default_params()
+    tuning = dict(chunk_pairs=65536)
+    print("[case] overflow two=%s" % two, flush=True)
+    parts = [_skewed_stream(5), _skewed_stream(6), _skewed_stream(7)]
+    earlier = _streams(8, [200_000])[0]
+    table, cubes = [], []
+    for i, q in enumerate(parts):
+        a = cb.new_cube(p)
+        b = cb.new_cube(p) if two else None
+        if i == 2:   # OR onto cubes holding earlier bits
+            if two:
+                cb.cbaa_update2(p, a, b, cb.pairs_to_device(earlier))
+            else:
+                cb.cbaa_update(p, a, cb.pairs_to_device(earlier), cb.SIDE_DST)
+        cubes.append((a, b))
+        side = cb.SIDE_SRC if two or i == 0 else cb.SIDE_DST
+        table.append((cb.pairs_to_device(q), a, b, side, 0 if i == 2 else cb.BATCH_FRESH))
+    scratch = cb.scratch_tensor(cb.cbaa_update_batch_scratch_bytes(p, table, tuning))
+    cb.cbaa_update_batch(p, table, scratch, tuning)
+    torch.cuda.synchronize()
+    for i, (q, (a, b)) in enumerate(zip(parts, cubes)):
+        src = np.concatenate([earlier, q]) if i == 2 else q
+        side = 0 if two or i == 0 else 1
+        assert np.array_equal(cb.cube_to_numpy(a), O.cube_of(p, src, side)), i
+        if two:
+            assert np.array_equal(cb.cube_to_numpy(b), O.cube_of(p, src, 1)), i
