@@ -43,11 +43,11 @@ HBM_PEAK_GBS = 8000.0
 # tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
 # valid only while the update kernels' sources are the ones measured
 # (profiles/update_core_edge_64M_traffic.txt).
-UPDATE_TRAFFIC = {"bytes": 4039025391, "sources": {
+UPDATE_TRAFFIC = {"bytes": 3445856236, "sources": {
     "paper_1901_06207_amd/csrc/cbaa_partition.hip":
-        "dbe08ac0c88b2976d6bcf520c4f61fe550356c8b80fdab2d6dc77f35fedb033d",
+        "0ce0a61807a16e137a010fe32b163205d80102d7a35cea372f0e351f2350f54f",
     "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
-        "6f403f6d6f8c1be7f01b02e96da5676cf36826744c3bbdc98ea5754fd46e6bdd"}}
+        "7bc6bddec7549e62da7edccbed38e3968c2320e60c670a1daea9951f0bd5d7d3"}}
 
 
 def measured_traffic(record, default_workload):

@@ -13,8 +13,8 @@
 //                  the stream, plus a margin for the sampling error) and the
 //                  prefix of the regions; the bins' write cursors start at
 //                  their bases. A bin's records are contiguous in its region.
-//   3. scatter     persistent blocks (one per CU, 768 threads) take scatter
-//                  chunks (20 pairs per thread), kept in registers, from a
+//   3. scatter     persistent blocks (one per CU, 1024 threads) take scatter
+//                  chunks (16 pairs per thread), kept in registers, from a
 //                  shared counter; per cube, rank the chunk's records inside
 //                  their bins in LDS, reserve each bin's run with one atomic
 //                  add on its cursor, stage the records bin-sorted and write
@@ -48,16 +48,16 @@ constexpr uint32_t kMaxBins = 8192;      // bins of a stream (both cubes)
 constexpr int kUnroll = 8;                // independent loads in flight per thread
 constexpr int kApplyUnroll = 16;
 constexpr uint32_t kMaxTileWords = 16384; // 128 KiB LDS tile
-// Scatter blocks of 768 threads (12 waves) have 168 registers per lane: a
-// chunk of 20 pairs per thread stays in registers with no spill, and its
-// 8-byte records fill 120 KiB of LDS next to 24 KiB of per-bin counters, run
-// offsets and region ends for up to 1024 bins per cube. Cubes of up to 4096
-// bins (e.g. 32 sketches, or 8192-bit columns) take 14 pairs per thread
-// beside 64 KiB.
-constexpr int kScatterThreads = 768;
+// Scatter blocks of 1024 threads (16 waves, 128 registers per lane): a chunk
+// of 16 pairs per thread stays in registers with no spill, and its 8-byte
+// records fill 128 KiB of LDS next to 24 KiB of per-bin counters, run offsets
+// and region ends for up to 1024 bins per cube. Cubes of up to 4096 bins
+// (e.g. 32 sketches, or 8192-bit columns) take 11 pairs per thread beside
+// 64 KiB.
+constexpr int kScatterThreads = 1024;
 constexpr uint32_t kSmallBins = 1024;     // bins per cube of the first shape
-constexpr int kScatterPerSmall = 20;
-constexpr int kScatterPerLarge = 14;
+constexpr int kScatterPerSmall = 16;
+constexpr int kScatterPerLarge = 11;
 inline uint32_t scatter_chunk(uint32_t per_cube) {
   return (per_cube <= kSmallBins ? kScatterPerSmall : kScatterPerLarge) * kScatterThreads;
 }
@@ -219,13 +219,13 @@ __device__ inline uint32_t bin_of(const Dims& d, uint32_t k, uint32_t host, uint
   const uint32_t b = bit_of_peer(d, peer);
   rec = make_uint2(m, b | (k << 31));
   const uint32_t cs = m & low_mask(d.r);
-  return (k * d.S + cs) * d.R + (b >> 6);
+  return ((((k << d.r) | cs) << (d.log2_g - 6)) | (b >> 6));   // (k S + cs) R + b / 64
 }
 
 __device__ inline uint32_t bin_of_record(const Dims& d, uint2 rec) {
   const uint32_t k = rec.y >> 31;
   const uint32_t b = rec.y & 0x7FFFFFFFu;
-  return (k * d.S + (rec.x & low_mask(d.r))) * d.R + (b >> 6);
+  return ((((k << d.r) | (rec.x & low_mask(d.r))) << (d.log2_g - 6)) | (b >> 6));
 }
 
 // Zeroes the bin totals and counters, and sets the streams' cube headers: a
@@ -408,7 +408,11 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, ui
   // second reads them with the cursor adds.
   constexpr bool kEndsInLds = NB <= kSmallBins;
   constexpr uint32_t kEndsWords = kEndsInLds ? 2 * NB : 0;
-  constexpr uint32_t kStageWord = 4 * NB + kEndsWords + kScatterThreads / kWave;
+  // ... then the scan's per-wave sums, a counter that absorbs the ranks of
+  // a short chunk's empty slots (so that every slot's LDS add is issued
+  // unconditionally and the adds stay in flight together), and padding
+  constexpr uint32_t kSpill = 4 * NB + kEndsWords + kScatterThreads / kWave;
+  constexpr uint32_t kStageWord = kSpill + 2;
   static_assert(kStageWord % 2 == 0, "stage must be 8-byte aligned");
   __shared__ __align__(16) uint32_t lds[kStageWord + 2 * P];
   uint32_t* cnt = lds;              // counts, then the end of the run's in-region part
@@ -417,6 +421,7 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, ui
   uint32_t* dov = lds + 3 * NB;     // overflow position of a stage slot, minus the slot
   uint32_t* ends = lds + 4 * NB;    // region ends of both cubes (first shape)
   uint32_t* waves = lds + 4 * NB + kEndsWords;
+  uint32_t* spill = lds + kSpill;
   uint2* stage = (uint2*)(lds + kStageWord);
   uint32_t ends_of = 0xFFFFFFFFu;   // stream whose ends are in LDS
   // bins per thread in the count scan
@@ -469,11 +474,17 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, ui
       for (int u = 0; u < (kPer + 1) / 2; ++u) rk[u] = 0;
 #pragma unroll
       for (int u = 0; u < kPer; ++u) {
-        const uint32_t h0 = k == 0 ? p[u].x : p[u].y;
-        const uint32_t p0 = k == 0 ? p[u].y : p[u].x;
+        uint32_t h0 = k == 0 ? p[u].x : p[u].y;
+        uint32_t p0 = k == 0 ? p[u].y : p[u].x;
+        // opaque to the compiler (no instruction): the staging pass below
+        // hashes the pair again instead of keeping this pass's bins live
+        // across the scan, which would spill
+        asm volatile("" : "+v"(h0), "+v"(p0));
         uint2 r;
         const uint32_t bl = bin_of(d, k, h0, p0, r) - k * per_cube;
-        const uint32_t rank = threadIdx.x + u * kScatterThreads < rem ? atomicAdd(&cnt[bl], 1u) : kNoRank;
+        const bool valid = threadIdx.x + u * kScatterThreads < rem;
+        const uint32_t got = atomicAdd(valid ? &cnt[bl] : spill, 1u);
+        const uint32_t rank = valid ? got : kNoRank;
         rk[u / 2] = pack_rank(rk[u / 2], u, rank);
       }
       __syncthreads();
