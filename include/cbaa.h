@@ -318,6 +318,31 @@ int cbaa_merge_restore(const cbaa_config* h_cfg, void* d_dst, const void* const*
                        uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
                        cbaa_restore_stats* d_stats, void* stream);
 
+/* cbaa_merge_restore in two calls, so that a caller can order the
+ * bandwidth-bound half of one window end against other work: for instance
+ * the two sides of a window on two streams, the second side's merge scan
+ * waiting (on an event) for the first side's, so that it runs while the
+ * first side's latency-bound tuple check does.
+ * cbaa_merge_scan: the OR-merge of the k sources (stored in d_dst unless it
+ * is NULL), the column scan, the thresholds (Thm. 1, Thm. 2) and the hot
+ * column lists (Alg. 2), kept in d_scratch.
+ * cbaa_restore_scanned: the rest of the restore (Alg. 3's tuple check and
+ * the ordered list) from that scratch.
+ * Both take exactly cbaa_merge_restore's arguments, and the pair gives its
+ * result, provided that the second call names the same configuration,
+ * destination, sources, scratch, capacity and stats as the first, runs after
+ * it in stream order, and no call in between writes the sources, the
+ * destination or the scratch. Each checks its arguments as cbaa_merge_restore
+ * does; the scan leaves d_out untouched. */
+int cbaa_merge_scan(const cbaa_config* h_cfg, void* d_dst, const void* const* h_srcs, int k,
+                    double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
+                    uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
+                    cbaa_restore_stats* d_stats, void* stream);
+int cbaa_restore_scanned(const cbaa_config* h_cfg, void* d_dst, const void* const* h_srcs, int k,
+                         double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
+                         uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
+                         cbaa_restore_stats* d_stats, void* stream);
+
 /* For callers that cannot allocate device memory (code under HIP graph
  * capture, tight serving loops, harnesses that forbid hipMalloc):
  * cbaa_merge_restore without a scratch argument. Its scratch is an array of

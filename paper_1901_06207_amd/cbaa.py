@@ -161,6 +161,10 @@ def lib():
         "cbaa_estimate": (i32, [cfgp, vp, vp, u64, vp, vp, vp, vp, u64, vp]),
         "cbaa_merge_restore": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, u64, vp, u64, vp, u64,
                                      vp, vp]),
+        "cbaa_merge_scan": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, u64, vp, u64, vp, u64,
+                                  vp, vp]),
+        "cbaa_restore_scanned": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, u64, vp, u64, vp,
+                                       u64, vp, vp]),
         "cbaa_merge_restore_noalloc": (i32, [cfgp, vp, C.POINTER(vp), i32, dbl, i32, u64, vp, u64,
                                              vp, vp]),
         "cbaa_mlp_param_count": (C.c_uint32, [C.c_uint32]),
@@ -386,6 +390,36 @@ def cbaa_merge_restore(cfg, dst: Optional[torch.Tensor], srcs: Sequence[torch.Te
                                     else None, capacity,
                                     _dev_ptr(stats, "stats", STATS_BYTES), _stream(stream)),
            "cbaa_merge_restore")
+
+
+def _merge_phase(name, cfg, dst, srcs, theta, rule, scratch, out, capacity, stats, stream,
+                 max_checks):
+    arr = (C.c_void_p * len(srcs))(*[_cube_ptr(cfg, x, "src") for x in srcs])
+    sb = scratch.numel() * scratch.element_size()
+    _check(getattr(lib(), name)(C.byref(_cfg(cfg)),
+                                _cube_ptr(cfg, dst, "dst") if dst is not None else None,
+                                arr, len(srcs), float(theta), rule, max_checks,
+                                _dev_ptr(scratch, "scratch"), sb,
+                                _dev_ptr(out, "out", capacity * HOST_BYTES) if capacity else None,
+                                capacity, _dev_ptr(stats, "stats", STATS_BYTES), _stream(stream)),
+           name)
+
+
+def cbaa_merge_scan(cfg, dst: Optional[torch.Tensor], srcs: Sequence[torch.Tensor],
+                    theta: float, rule: int, scratch: torch.Tensor, out: Optional[torch.Tensor],
+                    capacity: int, stats: torch.Tensor, stream=None, max_checks: int = 0) -> None:
+    """First half of cbaa_merge_restore (merge and column scan)."""
+    _merge_phase("cbaa_merge_scan", cfg, dst, srcs, theta, rule, scratch, out, capacity, stats,
+                 stream, max_checks)
+
+
+def cbaa_restore_scanned(cfg, dst: Optional[torch.Tensor], srcs: Sequence[torch.Tensor],
+                         theta: float, rule: int, scratch: torch.Tensor,
+                         out: Optional[torch.Tensor], capacity: int, stats: torch.Tensor,
+                         stream=None, max_checks: int = 0) -> None:
+    """Second half of cbaa_merge_restore, with the same arguments as the first."""
+    _merge_phase("cbaa_restore_scanned", cfg, dst, srcs, theta, rule, scratch, out, capacity,
+                 stats, stream, max_checks)
 
 
 def cbaa_merge_restore_noalloc(cfg, dst: Optional[torch.Tensor], srcs: Sequence[torch.Tensor],

@@ -360,10 +360,14 @@ int cbaa_restore(const cbaa_config* cfg, const void* d_cube, double theta, int t
 
 // Argument checks and launch of the window end, shared by cbaa_merge_restore
 // (caller's scratch) and cbaa_merge_restore_noalloc (the library's array).
+// Which part of the window end a call runs.
+enum MergePhase { kBoth, kScanOnly, kRestoreOnly };
+
 static int merge_restore_checked(const Dims& d, void* d_dst, const void* const* h_srcs, int k,
                                  double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
                                  uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
-                                 cbaa_restore_stats* d_stats, void* stream) {
+                                 cbaa_restore_stats* d_stats, void* stream,
+                                 MergePhase phase = kBoth) {
   // a null destination (merge not stored) is served by the one-pass scan,
   // which takes up to 16 sources
   REQUIRE(((uintptr_t)d_dst & 15u) == 0, "destination must be 16-byte aligned");
@@ -387,9 +391,16 @@ static int merge_restore_checked(const Dims& d, void* d_dst, const void* const* 
   const uint64_t* stack[64];
   const uint64_t** b = k <= 64 ? stack : new const uint64_t*[k];
   for (int i = 0; i < k; ++i) b[i] = bits_of(h_srcs[i]);
-  const int rc = launch_merge_restore(d, bits_of(d_dst), b, k, x, thr_rule,
-                                      max_checks ? max_checks : CBAA_DEFAULT_MAX_CHECKS,
-                                      d_scratch, capacity, d_out, d_stats, (hipStream_t)stream);
+  const uint64_t mc = max_checks ? max_checks : CBAA_DEFAULT_MAX_CHECKS;
+  const hipStream_t s = (hipStream_t)stream;
+  const int rc =
+      phase == kScanOnly
+          ? launch_merge_scan(d, bits_of(d_dst), b, k, x, thr_rule, d_scratch, capacity, d_stats, s)
+      : phase == kRestoreOnly
+          ? launch_restore_scanned(d, bits_of(d_dst), b, k, mc, d_scratch, capacity, d_out,
+                                   d_stats, s)
+          : launch_merge_restore(d, bits_of(d_dst), b, k, x, thr_rule, mc, d_scratch, capacity,
+                                 d_out, d_stats, s);
   if (b != stack) delete[] b;
   return rc;
 }
@@ -401,6 +412,24 @@ int cbaa_merge_restore(const cbaa_config* cfg, void* d_dst, const void* const* h
   CHECK_DIMS(cfg, d);
   return merge_restore_checked(d, d_dst, h_srcs, k, theta, thr_rule, max_checks, d_scratch,
                                scratch_bytes, d_out, capacity, d_stats, stream);
+}
+
+int cbaa_merge_scan(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
+                    double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
+                    uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
+                    cbaa_restore_stats* d_stats, void* stream) {
+  CHECK_DIMS(cfg, d);
+  return merge_restore_checked(d, d_dst, h_srcs, k, theta, thr_rule, max_checks, d_scratch,
+                               scratch_bytes, d_out, capacity, d_stats, stream, kScanOnly);
+}
+
+int cbaa_restore_scanned(const cbaa_config* cfg, void* d_dst, const void* const* h_srcs, int k,
+                         double theta, int thr_rule, uint64_t max_checks, void* d_scratch,
+                         uint64_t scratch_bytes, cbaa_host* d_out, uint64_t capacity,
+                         cbaa_restore_stats* d_stats, void* stream) {
+  CHECK_DIMS(cfg, d);
+  return merge_restore_checked(d, d_dst, h_srcs, k, theta, thr_rule, max_checks, d_scratch,
+                               scratch_bytes, d_out, capacity, d_stats, stream, kRestoreOnly);
 }
 
 }  // extern "C"

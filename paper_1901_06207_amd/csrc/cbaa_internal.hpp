@@ -176,6 +176,15 @@ uint64_t restore_scratch_bytes(const Dims& d, uint64_t capacity);
 int launch_restore(const Dims& d, const uint64_t* cube, double x_theta, int rule,
                    uint64_t max_checks, void* scratch, uint64_t capacity, cbaa_host* out,
                    cbaa_restore_stats* stats, hipStream_t s);
+// The two halves of launch_merge_restore: reset, OR-merge, column scan,
+// thresholds and hot lists (Alg. 2); then the tuple check (Alg. 3) and the
+// ordering from the scratch the first half filled.
+int launch_merge_scan(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
+                      double x_theta, int rule, void* scratch, uint64_t capacity,
+                      cbaa_restore_stats* stats, hipStream_t s);
+int launch_restore_scanned(const Dims& d, const uint64_t* dst, const uint64_t* const* srcs,
+                           int k, uint64_t max_checks, void* scratch, uint64_t capacity,
+                           cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s);
 int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
                          double x_theta, int rule, uint64_t max_checks, void* scratch,
                          uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats,

@@ -1325,16 +1325,20 @@ int launch_column_zeros(const Dims& d, const uint64_t* cube, uint16_t* zeros, ui
 
 namespace {
 
-// Everything after the column scan: thresholds, hot lists and gather, join,
-// ordering.
-int restore_after_scan(const Dims& d, const CubeSrc& cube, double x, int rule,
-                       uint64_t max_checks, const RestoreScratch& rs, uint64_t capacity,
-                       cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s) {
-  int rc;
+// After the column scan: thresholds, hot lists and their gather (Alg. 2).
+int find_hot(const Dims& d, const CubeSrc& cube, double x, int rule, const RestoreScratch& rs,
+             cbaa_restore_stats* stats, hipStream_t s) {
   hipLaunchKernelGGL(k_prepare, dim3(d.S, d.n_ra, kPrepParts), dim3(kPrepBlock), 0, s, d,
                      rs.zeros, rs.ones, rs.eps, rs.zmax, rs.hcnt, rs.hot, x, rule, stats, cube,
                      rs.hcol, rs.gcap, rs.gfit);
-  if ((rc = check_launch("prepare launch")) != CBAA_OK) return rc;
+  return check_launch("prepare launch");
+}
+
+// After the hot lists: the tuple check (Alg. 3) and the ordering.
+int join_and_order(const Dims& d, const CubeSrc& cube, uint64_t max_checks,
+                   const RestoreScratch& rs, uint64_t capacity, cbaa_host* out,
+                   cbaa_restore_stats* stats, hipStream_t s) {
+  int rc;
   JoinArgs ja{cube,     rs.zeros,  rs.hot,  rs.hcol, rs.gfit,  rs.gcap,  rs.hcnt, rs.zmax,
               rs.eps,   rs.stage,  rs.wbuf, rs.wcnt, capacity, stats,    rs.work, max_checks};
   if ((rc = run_join(d, ja, s)) != CBAA_OK) return rc;
@@ -1364,6 +1368,33 @@ int restore_after_scan(const Dims& d, const CubeSrc& cube, double x, int rule,
   return check_launch("sort launches");
 }
 
+// Everything after the column scan.
+int restore_after_scan(const Dims& d, const CubeSrc& cube, double x, int rule,
+                       uint64_t max_checks, const RestoreScratch& rs, uint64_t capacity,
+                       cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s) {
+  const int rc = find_hot(d, cube, x, rule, rs, stats, s);
+  if (rc != CBAA_OK) return rc;
+  return join_and_order(d, cube, max_checks, rs, capacity, out, stats, s);
+}
+
+// The sources the restore reads: the merged cube when stored, else the
+// router cubes (OR-ed on every read).
+bool restore_sources(const uint64_t* dst, const uint64_t* const* srcs, int k, CubeSrc& cs) {
+  cs = CubeSrc{};
+  if (dst) {
+    cs.p[0] = dst;
+    cs.k = 1;
+    return true;
+  }
+  if (k > kMergeScanSources) {
+    set_error("more than %d source cubes need a destination cube", kMergeScanSources);
+    return false;
+  }
+  for (int j = 0; j < k; ++j) cs.p[j] = srcs[j];
+  cs.k = k;
+  return true;
+}
+
 }  // namespace
 
 int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, uint64_t max_checks,
@@ -1378,27 +1409,24 @@ int launch_restore(const Dims& d, const uint64_t* cube, double x, int rule, uint
   return restore_after_scan(d, one, x, rule, max_checks, rs, capacity, out, stats, s);
 }
 
-int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
-                         double x, int rule, uint64_t max_checks, void* scratch,
-                         uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats,
-                         hipStream_t s) {
-  if (k > kMergeScanSources) {   // merge in passes first, then the plain restore
-    if (!dst) {
-      set_error("more than %d source cubes need a destination cube", kMergeScanSources);
-      return CBAA_EINVAL;
-    }
-    const int rc = launch_merge_or(d, dst, srcs, k, s);
-    if (rc != CBAA_OK) return rc;
-    return launch_restore(d, dst, x, rule, max_checks, scratch, capacity, out, stats, s);
-  }
+int launch_merge_scan(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
+                      double x, int rule, void* scratch, uint64_t capacity,
+                      cbaa_restore_stats* stats, hipStream_t s) {
   RestoreScratch rs = carve(d, scratch, capacity);
+  CubeSrc cs;
+  if (!restore_sources(dst, srcs, k, cs)) return CBAA_EINVAL;
+  int rc;
+  if (k > kMergeScanSources) {   // merge in passes first, then the plain scan
+    if ((rc = launch_merge_or(d, dst, srcs, k, s)) != CBAA_OK) return rc;
+    if ((rc = run_scan(d, dst, rs.zeros, rs.ones, stats, rs.work, s)) != CBAA_OK) return rc;
+    return find_hot(d, cs, x, rule, rs, stats, s);
+  }
   CubeSrc all{};
   for (int j = 0; j < k; ++j) all.p[j] = srcs[j];
   all.k = k;
   hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, d, stats, rs.ones, d.S * d.A, rs.work, all,
                      dst);
-  int rc = check_launch("reset launch");
-  if (rc != CBAA_OK) return rc;
+  if ((rc = check_launch("reset launch")) != CBAA_OK) return rc;
   MergeSrc ms{};
   for (int j = 0; j < k; ++j) ms.p[j] = (const uint4*)srcs[j];
   const uint32_t half_w = d.W / 2;
@@ -1406,15 +1434,25 @@ int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* sr
   hipLaunchKernelGGL(k_merge_scan, grid, dim3(kScanBlock), 0, s, d, ms, k, (uint4*)dst,
                      (uint32_t*)rs.zeros, rs.ones);
   if ((rc = check_launch("merge scan launch")) != CBAA_OK) return rc;
-  CubeSrc cs{};
-  if (dst) {
-    cs.p[0] = dst;
-    cs.k = 1;
-  } else {   // the merge is not stored: later reads OR the sources
-    for (int j = 0; j < k; ++j) cs.p[j] = srcs[j];
-    cs.k = k;
-  }
-  return restore_after_scan(d, cs, x, rule, max_checks, rs, capacity, out, stats, s);
+  return find_hot(d, cs, x, rule, rs, stats, s);
+}
+
+int launch_restore_scanned(const Dims& d, const uint64_t* dst, const uint64_t* const* srcs,
+                           int k, uint64_t max_checks, void* scratch, uint64_t capacity,
+                           cbaa_host* out, cbaa_restore_stats* stats, hipStream_t s) {
+  RestoreScratch rs = carve(d, scratch, capacity);
+  CubeSrc cs;
+  if (!restore_sources(dst, srcs, k, cs)) return CBAA_EINVAL;
+  return join_and_order(d, cs, max_checks, rs, capacity, out, stats, s);
+}
+
+int launch_merge_restore(const Dims& d, uint64_t* dst, const uint64_t* const* srcs, int k,
+                         double x, int rule, uint64_t max_checks, void* scratch,
+                         uint64_t capacity, cbaa_host* out, cbaa_restore_stats* stats,
+                         hipStream_t s) {
+  const int rc = launch_merge_scan(d, dst, srcs, k, x, rule, scratch, capacity, stats, s);
+  if (rc != CBAA_OK) return rc;
+  return launch_restore_scanned(d, dst, srcs, k, max_checks, scratch, capacity, out, stats, s);
 }
 
 int launch_estimate(const Dims& d, const uint64_t* cube, const uint32_t* hosts, uint64_t n,

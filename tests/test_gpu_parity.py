@@ -534,3 +534,72 @@ def test_g8192_update_restore_estimate(cb, path):
     west, wz, _ = O.estimate(p, want_cube, hosts)
     assert np.array_equal(zeros, wz)
     assert np.all(np.abs(est - west) <= EST_RTOL * np.maximum(1.0, west))
+
+
+@pytest.mark.parametrize("k,stored", [(2, False), (3, True), (16, False), (17, True)])
+def test_merge_scan_then_restore_scanned_equals_the_fused_call(cb, k, stored):
+    """The window end in two calls (merge, column scan and hot lists; then
+    the tuple check and ordering from the scratch) gives the fused call's
+    cube, stats and host list, and the oracle's hosts."""
+    import torch
+    p = default_params()
+    t = tracegen.window_small(9)
+    parts = tracegen.split_routers(t.pairs, k, seed=9)
+    srcs = [_gpu_cube(cb, p, q, 0) for q in parts]
+    _say("merge scan + restore scanned", k, stored)
+    ref, st_ref = _merge_restore(cb, p, cb.new_cube(p, init=False) if stored else None, srcs)
+    cap = 4096
+    dst = cb.new_cube(p, init=False) if stored else None
+    rs = cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, cap))
+    out = torch.empty(cap * 16, dtype=torch.uint8, device="cuda")
+    st = cb.stats_tensor()
+    cb.cbaa_merge_scan(p, dst, srcs, 1024.0, cb.THR_THM2, rs, out, cap, st)
+    cb.cbaa_restore_scanned(p, dst, srcs, 1024.0, cb.THR_THM2, rs, out, cap, st)
+    torch.cuda.synchronize()
+    assert np.array_equal(st.cpu().numpy(), st_ref)
+    got = cb.host_list(out, int(st[0]))
+    _assert_hosts_equal(got, ref)
+    want_cube = O.cube_of(p, t.pairs, 0)
+    if stored:
+        assert np.array_equal(cb.cube_to_numpy(dst), want_cube)
+    want, _ = O.restore(p, want_cube, 1024.0)
+    _assert_hosts_equal(got, want)
+
+
+def test_two_sides_with_the_second_scan_after_the_first(cb):
+    """Both sides of a window on two streams, the second side's merge scan
+    waiting on an event after the first side's hot lists, each side's tuple
+    check after its own scan: both lists equal the fused calls' and the
+    oracle's."""
+    import torch
+    p = default_params()
+    t = tracegen.window_small(10)
+    parts = tracegen.split_routers(t.pairs, 2, seed=10)
+    local = [(_gpu_cube(cb, p, q, 0), _gpu_cube(cb, p, q, 1)) for q in parts]
+    cap = 4096
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    rs = [cb.scratch_tensor(cb.cbaa_restore_scratch_bytes(p, cap)) for _ in range(2)]
+    outs = [torch.empty(cap * 16, dtype=torch.uint8, device="cuda") for _ in range(2)]
+    sts = [cb.stats_tensor() for _ in range(2)]
+    _say("two sides, ordered scans")
+    fork = torch.cuda.Event()
+    fork.record(torch.cuda.current_stream())
+    for s_ in streams:
+        s_.wait_event(fork)
+    args = [(p, None, [x[i] for x in local], 1024.0, cb.THR_THM2, rs[i], outs[i], cap, sts[i],
+             streams[i]) for i in range(2)]
+    cb.cbaa_merge_scan(*args[0])
+    scanned = torch.cuda.Event()
+    scanned.record(streams[0])
+    streams[1].wait_event(scanned)
+    cb.cbaa_merge_scan(*args[1])
+    cb.cbaa_restore_scanned(*args[0])
+    cb.cbaa_restore_scanned(*args[1])
+    torch.cuda.synchronize()
+    for side in range(2):
+        got = cb.host_list(outs[side], int(sts[side][0]))
+        ref, st_ref = _merge_restore(cb, p, None, [x[side] for x in local])
+        assert np.array_equal(sts[side].cpu().numpy(), st_ref)
+        _assert_hosts_equal(got, ref)
+        want, _ = O.restore(p, O.cube_of(p, t.pairs, side), 1024.0)
+        _assert_hosts_equal(got, want)
