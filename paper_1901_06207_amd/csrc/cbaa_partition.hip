@@ -22,9 +22,9 @@
 //                  whatever the atomics give: the OR of the bits does not
 //                  depend on it. Records past the end of a full region go to
 //                  the stream's overflow list instead
-//   4. fills       per stream: each region's fill and the exclusive prefix of
-//                  the apply segments; then the apply items prefixed over
-//                  streams
+//   4. fills       per stream: each region's fill, the exclusive prefix of
+//                  the apply segments and the fresh row blocks to zero; the
+//                  last stream to finish prefixes the apply items over streams
 //   5. apply       persistent blocks take (stream, bin, segment) items from a
 //                  shared counter (work stealing across streams): zero
 //                  an LDS tile, OR the records' bits into it, flush non-zero
@@ -105,6 +105,8 @@ struct Layout {
   uint32_t* tot;      // [k][nbins] sampled records per bin, later each region's fill
   uint32_t* next;     // [2] next apply item, next scatter chunk (right after tot)
   uint32_t* ovfn;     // [k] entries of each stream's overflow list (right after next)
+  uint32_t* nclear;   // [2] fresh row blocks to zero, streams whose fills are done (after ovfn)
+  uint32_t* clear;    // [k][nbins] fresh row blocks to zero: stream << 16 | bin
   uint32_t* cursor;   // [k][nbins] next free record of each bin (scatter)
   uint32_t* base;     // [k][nbins + 1] record offsets inside the stream
   uint32_t* segpre;   // [k][nbins + 1] apply items inside the stream
@@ -184,9 +186,11 @@ Layout plan(const Dims& d, int n_cubes, uint32_t chunk, Batch& b, void* base) {
     off += align256(bytes);
     return (void*)q;
   };
-  L.tot = (uint32_t*)take(((uint64_t)b.k * b.nbins + 2 + b.k) * 4);
+  L.tot = (uint32_t*)take(((uint64_t)b.k * b.nbins + 2 + b.k + 2) * 4);
   L.next = L.tot + (uint64_t)b.k * b.nbins;
   L.ovfn = L.next + 2;
+  L.nclear = L.ovfn + b.k;
+  L.clear = (uint32_t*)take((uint64_t)b.k * b.nbins * 4);
   L.cursor = (uint32_t*)take((uint64_t)b.k * b.nbins * 4);
   L.base = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
   L.segpre = (uint32_t*)take((uint64_t)b.k * (b.nbins + 1) * 4);
@@ -342,13 +346,20 @@ __global__ __launch_bounds__(kBlock) void k_bases(Batch b, const uint32_t* __res
 
 // Block si, after the scatter: each region's fill (its cursor, capped at the
 // region's end; the rest went to the overflow list), kept in tot, and the
-// exclusive prefix of the apply segments the fills need (segpre).
+// exclusive prefix of the apply segments the fills need (segpre). A fresh
+// stream's bins that no single apply item will store whole (no records, or
+// several items) go to the clear list. The last block to finish prefixes the
+// streams' apply items.
 __global__ __launch_bounds__(kBlock) void k_fills(Batch b, const uint32_t* __restrict__ base,
                                                   const uint32_t* __restrict__ cursor,
-                                                  uint32_t* tot, uint32_t* segpre) {
+                                                  uint32_t* tot, uint32_t* segpre,
+                                                  uint32_t* clear, uint32_t* nclear,
+                                                  uint32_t* items) {
   __shared__ uint32_t waves[kBlock / kWave];
   __shared__ uint32_t carry;
+  __shared__ bool last;
   const uint32_t si = blockIdx.x;
+  const bool fresh = b.s[si].fresh != 0;
   const uint32_t* bs = base + (uint64_t)si * (b.nbins + 1);
   const uint32_t* cu = cursor + (uint64_t)si * b.nbins;
   uint32_t* t = tot + (uint64_t)si * b.nbins;
@@ -363,6 +374,9 @@ __global__ __launch_bounds__(kBlock) void k_fills(Batch b, const uint32_t* __res
       const uint32_t fill = (c < end ? c : end) - bs[bin];
       t[bin] = fill;
       nseg = (uint32_t)(((uint64_t)fill + b.seg - 1) / b.seg);
+      if (fresh && nseg != 1)
+        clear[__hip_atomic_fetch_add(nclear, 1u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)] =
+            (si << 16) | bin;
     }
     uint32_t sum;
     const uint32_t ex = block_exclusive_scan(nseg, waves, sum);
@@ -372,17 +386,22 @@ __global__ __launch_bounds__(kBlock) void k_fills(Batch b, const uint32_t* __res
     if (threadIdx.x == 0) carry = cr + sum;
     __syncthreads();
   }
-  if (threadIdx.x == 0) sp[b.nbins] = carry;
-}
-
-__global__ void k_stream_items(Batch b, const uint32_t* segpre, uint32_t* items) {
-  if (threadIdx.x != 0) return;
-  uint32_t acc = 0;
-  for (uint32_t si = 0; si < b.k; ++si) {
-    items[si] = acc;
-    acc += segpre[(uint64_t)si * (b.nbins + 1) + b.nbins];
+  if (threadIdx.x == 0) {
+    __hip_atomic_store(sp + b.nbins, carry, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    // the stream's total is visible before the count of finished streams
+    last = __hip_atomic_fetch_add(nclear + 1, 1u, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT) ==
+           b.k - 1;
   }
-  items[b.k] = acc;
+  __syncthreads();
+  if (last && threadIdx.x == 0) {
+    uint32_t acc = 0;
+    for (uint32_t j = 0; j < b.k; ++j) {
+      items[j] = acc;
+      acc += __hip_atomic_load(segpre + (uint64_t)j * (b.nbins + 1) + b.nbins, __ATOMIC_RELAXED,
+                               __HIP_MEMORY_SCOPE_AGENT);
+    }
+    items[b.k] = acc;
+  }
 }
 
 __device__ inline uint32_t pack_rank(uint32_t rk, int u, uint32_t rank) {
@@ -564,22 +583,27 @@ __global__ __launch_bounds__(kScatterThreads) void k_scatter(Dims d, Batch b, ui
   }
 }
 
-// Row blocks of fresh streams that the apply does not store whole: bins with
-// no records (no item) or with several items (OR-ed by each). Block (bin,
-// stream).
-__global__ __launch_bounds__(256) void k_clear_fresh(Dims d, Batch b,
-                                                     const uint32_t* __restrict__ segpre) {
-  const uint32_t bin = blockIdx.x, si = blockIdx.y;
-  const StreamDesc& st = b.s[si];
-  if (!st.fresh) return;
-  const uint32_t* sp = segpre + (uint64_t)si * (b.nbins + 1);
-  if (sp[bin + 1] - sp[bin] == 1) return;
+__device__ inline void clear_row_block(const Dims& d, const StreamDesc& st, uint32_t bin) {
   const uint32_t per_cube = d.S * d.R;
   uint64_t* cube = bin < per_cube ? st.cube0 : st.cube1;
   const uint32_t row = bin < per_cube ? bin : bin - per_cube;
   uint4* dst = (uint4*)(cube + (uint64_t)row * d.W);   // W is even, cubes 16-byte aligned
   for (uint32_t w = threadIdx.x; w < d.W / 2; w += 256) dst[w] = make_uint4(0u, 0u, 0u, 0u);
 }
+
+// Row blocks of fresh streams that the apply does not store whole (the clear
+// list: bins with no records, or with several items, each OR-ed): zeroed
+// before the apply. Blocks stride over the list.
+__global__ __launch_bounds__(256) void k_clear_fresh(Dims d, Batch b,
+                                                     const uint32_t* __restrict__ clear,
+                                                     const uint32_t* __restrict__ nclear) {
+  const uint32_t n = *nclear;
+  for (uint32_t e = blockIdx.x; e < n; e += gridDim.x) {
+    const uint32_t v = clear[e];
+    clear_row_block(d, b.s[v >> 16], v & 0xFFFFu);
+  }
+}
+
 
 // Largest x in [0, n) with tab[x] <= v (tab ascending, tab[0] <= v < tab[n]).
 __device__ inline uint32_t upper_index(const uint32_t* tab, uint32_t n, uint32_t v) {
@@ -728,8 +752,9 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
   int rc;
   bool any_fresh = false;
   for (uint32_t i = 0; i < b.k; ++i) any_fresh = any_fresh || b.s[i].fresh;
-  // sampled counts, the apply's and the scatter's counters, overflow counts
-  const uint32_t nt = b.k * b.nbins + 2 + b.k;
+  // sampled counts, the apply's and the scatter's counters, overflow counts,
+  // the clear list's length and the count of streams with their fills done
+  const uint32_t nt = b.k * b.nbins + 2 + b.k + 2;
   hipLaunchKernelGGL(k_begin, dim3((nt + 255) / 256), dim3(256), 0, s, d, b, L.tot, nt);
   if ((rc = check("begin launch")) != CBAA_OK) return rc;
   if (b.total_samples == 0) {   // no pairs at all: fresh cubes are just emptied
@@ -754,12 +779,11 @@ int run(const Dims& d, Batch& b, const Layout& L, uint32_t apply_blocks, hipStre
                        dim3(kScatterThreads), 0, s, d, b, L.cursor, L.base, L.rec, L.ovfn,
                        L.next + 1);
   if ((rc = check("scatter launch")) != CBAA_OK) return rc;
-  hipLaunchKernelGGL(k_fills, dim3(b.k), dim3(kBlock), 0, s, b, L.base, L.cursor, L.tot, L.segpre);
+  hipLaunchKernelGGL(k_fills, dim3(b.k), dim3(kBlock), 0, s, b, L.base, L.cursor, L.tot, L.segpre,
+                     L.clear, L.nclear, L.items);
   if ((rc = check("fills launch")) != CBAA_OK) return rc;
-  hipLaunchKernelGGL(k_stream_items, dim3(1), dim3(64), 0, s, b, L.segpre, L.items);
-  if ((rc = check("items launch")) != CBAA_OK) return rc;
   if (any_fresh) {
-    hipLaunchKernelGGL(k_clear_fresh, dim3(b.nbins, b.k), dim3(256), 0, s, d, b, L.segpre);
+    hipLaunchKernelGGL(k_clear_fresh, dim3(256), dim3(256), 0, s, d, b, L.clear, L.nclear);
     if ((rc = check("clear launch")) != CBAA_OK) return rc;
   }
   return run_apply(d, b, L, apply_blocks, s);
