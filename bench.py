@@ -157,16 +157,20 @@ def main():
     capacity = 1 << 14
     rs_bytes = cbaa.cbaa_restore_scratch_bytes(cfg, capacity)
     scratch_r = [cbaa.scratch_tensor(rs_bytes, dev) for _ in range(2)]
-    # both sides' lists and counters in one device buffer, so that the step
-    # brings its results to the host with one copy: [list 0 | list 1 | stats]
+    # each side's list and counters contiguous in one device buffer,
+    # [list 0 | stats 0 | list 1 | stats 1], so that a side's results come
+    # back with one copy (both sides' with one when the sides run in order)
     lb = capacity * cbaa.HOST_BYTES
     sb = cbaa.STATS_BYTES
-    d_res = torch.empty(2 * lb + 2 * sb, dtype=torch.uint8, device=dev)
-    h_res = torch.empty(2 * lb + 2 * sb, dtype=torch.uint8, pin_memory=True)
-    outs = [d_res[i * lb:(i + 1) * lb] for i in range(2)]
-    stats = [d_res[2 * lb + sb * i: 2 * lb + sb * (i + 1)].view(torch.int64) for i in range(2)]
-    h_outs = [h_res[i * lb:(i + 1) * lb] for i in range(2)]
-    h_stats = [h_res[2 * lb + sb * i: 2 * lb + sb * (i + 1)].view(torch.int64) for i in range(2)]
+    pb = (lb + sb + 255) // 256 * 256
+    d_res = torch.empty(2 * pb, dtype=torch.uint8, device=dev)
+    h_res = torch.empty(2 * pb, dtype=torch.uint8, pin_memory=True)
+    outs = [d_res[i * pb: i * pb + lb] for i in range(2)]
+    stats = [d_res[i * pb + lb: i * pb + lb + sb].view(torch.int64) for i in range(2)]
+    h_outs = [h_res[i * pb: i * pb + lb] for i in range(2)]
+    h_stats = [h_res[i * pb + lb: i * pb + lb + sb].view(torch.int64) for i in range(2)]
+    d_sides = [d_res[i * pb: (i + 1) * pb] for i in range(2)]
+    h_sides = [h_res[i * pb: (i + 1) * pb] for i in range(2)]
 
     ev = {}
 
@@ -221,6 +225,10 @@ def main():
             cbaa.cbaa_merge_scan(*side_args[1], wstreams[1])
             cbaa.cbaa_restore_scanned(*side_args[0], wstreams[0])
             cbaa.cbaa_restore_scanned(*side_args[1], wstreams[1])
+            # each side's list to the host as soon as that side is done
+            for i, st in enumerate(wstreams):
+                with torch.cuda.stream(st):
+                    h_sides[i].copy_(d_sides[i], non_blocking=True)
         else:
             for a in side_args:
                 cbaa.cbaa_merge_restore(*a, stream)
@@ -231,8 +239,9 @@ def main():
                 stream.wait_event(e)
         if timed:
             mark("copy", stream)
-        with torch.cuda.stream(stream):
-            h_res.copy_(d_res, non_blocking=True)
+        if not overlap:
+            with torch.cuda.stream(stream):
+                h_res.copy_(d_res, non_blocking=True)
         if timed:
             mark("end", stream)
 

@@ -953,21 +953,46 @@ __global__ __launch_bounds__(kCompactBlock) void k_compact(const cbaa_host* __re
 // keeps keys unique regardless. The rank of a key is the number of smaller
 // keys, and the entry is written there.
 
-// Lists of at most kSmallSort entries: one wave per entry counts the smaller
-// keys over the whole list and writes the entry at that rank.
+// Lists of at most kSmallSort entries: each wave takes kRankPerWave entries
+// and counts, for each, the smaller keys over the whole list, which the
+// block streams through LDS in tiles; each entry is written at its rank.
+constexpr uint32_t kRankPerWave = 4;
+constexpr uint32_t kRankTile = 2048;   // keys per LDS tile (16 KiB)
 __global__ __launch_bounds__(256) void k_rank_small(const cbaa_host* __restrict__ stage,
                                                     const cbaa_restore_stats* stats,
                                                     uint64_t capacity, cbaa_host* out) {
-  const uint64_t n = stats->n_hosts < capacity ? stats->n_hosts : capacity;
-  if (n > kSmallSort) return;
-  const uint32_t e = blockIdx.x * (256 / kWave) + threadIdx.x / kWave;
-  if (e >= n) return;
-  const uint64_t key = ((uint64_t)stage[e].ip << 32) | e;
-  uint32_t less = 0;
-  for (uint32_t j = lane_id(); j < n; j += kWave)
-    less += (((uint64_t)stage[j].ip << 32) | j) < key ? 1u : 0u;
-  const uint32_t rank = wave_sum(less);
-  if (lane_id() == 0) out[rank] = stage[e];
+  __shared__ uint64_t keys[kRankTile];
+  const uint64_t n64 = stats->n_hosts < capacity ? stats->n_hosts : capacity;
+  if (n64 > kSmallSort) return;
+  const uint32_t n = (uint32_t)n64;
+  const uint32_t e0 = (blockIdx.x * (256 / kWave) + threadIdx.x / kWave) * kRankPerWave;
+  if (blockIdx.x * (256 / kWave) * kRankPerWave >= n) return;   // uniform over the block
+  uint64_t mine[kRankPerWave];
+  uint32_t less[kRankPerWave];
+#pragma unroll
+  for (uint32_t q = 0; q < kRankPerWave; ++q) {
+    const uint32_t e = e0 + q;
+    mine[q] = e < n ? (((uint64_t)stage[e].ip << 32) | e) : ~0ull;
+    less[q] = 0;
+  }
+  for (uint32_t t0 = 0; t0 < n; t0 += kRankTile) {
+    const uint32_t m = n - t0 < kRankTile ? n - t0 : kRankTile;
+    __syncthreads();   // the previous tile is no longer read
+    for (uint32_t j = threadIdx.x; j < m; j += 256)
+      keys[j] = ((uint64_t)stage[t0 + j].ip << 32) | (t0 + j);
+    __syncthreads();
+    for (uint32_t j = lane_id(); j < m; j += kWave) {
+      const uint64_t k = keys[j];
+#pragma unroll
+      for (uint32_t q = 0; q < kRankPerWave; ++q) less[q] += k < mine[q] ? 1u : 0u;
+    }
+  }
+#pragma unroll
+  for (uint32_t q = 0; q < kRankPerWave; ++q) {
+    const uint32_t rank = wave_sum(less[q]);
+    const uint32_t e = e0 + q;
+    if (e < n && lane_id() == 0) out[rank] = stage[e];
+  }
 }
 
 // Larger lists: a counting sort into 2^16 buckets by the IP's top 16 bits,
@@ -1347,7 +1372,9 @@ int join_and_order(const Dims& d, const CubeSrc& cube, uint64_t max_checks,
   if ((rc = check_launch("compact launch")) != CBAA_OK) return rc;
   if (capacity == 0) return CBAA_OK;
   const uint64_t small = capacity < kSmallSort ? capacity : kSmallSort;
-  hipLaunchKernelGGL(k_rank_small, dim3((uint32_t)((small + 3) / 4)), dim3(256), 0, s, rs.stage,
+  const uint32_t per_block = (256 / kWave) * kRankPerWave;
+  hipLaunchKernelGGL(k_rank_small, dim3((uint32_t)((small + per_block - 1) / per_block)), dim3(256),
+                     0, s, rs.stage,
                      stats, capacity, out);
   if ((rc = check_launch("rank launch")) != CBAA_OK) return rc;
   // larger lists (each kernel returns at once when the list is small; none
