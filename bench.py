@@ -43,11 +43,11 @@ HBM_PEAK_GBS = 8000.0
 # tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
 # valid only while the update kernels' sources are the ones measured
 # (profiles/update_core_edge_64M_traffic.txt).
-UPDATE_TRAFFIC = {"bytes": 3443788530, "sources": {
+UPDATE_TRAFFIC = {"bytes": 3445876620, "sources": {
     "paper_1901_06207_amd/csrc/cbaa_partition.hip":
         "ccecc820ae0583c17206ba85520c86c516773b8787eafaeb17c141eab7d76224",
     "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
-        "d8de15a09a51fe3c7ece8491131b5ac464a3ae6b723eafddc06b4005d4ab2980"}}
+        "04742cfdeb7a9049a49c18455a2a890d340d8c3e9ea9799752d7d5507db85aca"}}
 
 
 def measured_traffic(record, default_workload):

@@ -32,6 +32,25 @@ struct Dims {
   uint64_t hash;              // cbaa_config_hash of the configuration
 };
 
+// ---- streaming access ----------------------------------------------------
+// Whole-cube passes (merge, column scan) read and write with the
+// non-temporal hint: the hundreds of MiB that pass through do not push out
+// of L2 what kernels running beside them (a restore's tuple check) keep
+// there.
+typedef uint32_t u32x4_stream __attribute__((ext_vector_type(4)));
+__device__ inline uint4 load_stream(const uint4* p) {
+  const u32x4_stream v = __builtin_nontemporal_load((const u32x4_stream*)p);
+  return make_uint4(v.x, v.y, v.z, v.w);
+}
+__device__ inline void store_stream(uint4* p, uint4 v) {
+  u32x4_stream w;
+  w.x = v.x;
+  w.y = v.y;
+  w.z = v.z;
+  w.w = v.w;
+  __builtin_nontemporal_store(w, (u32x4_stream*)p);
+}
+
 // ---- cube header ---------------------------------------------------------
 // Kernels receive the cube's bits; its header sits the 256 bytes before them.
 

@@ -131,7 +131,7 @@ __global__ __launch_bounds__(kScanBlock) void k_column_zeros(Dims d, const uint4
     for (; rb + kU <= d.R; rb += kU) {
       uint4 v[kU];
 #pragma unroll
-      for (uint32_t u = 0; u < kU; ++u) v[u] = p[(uint64_t)(rb + u) * half_w];
+      for (uint32_t u = 0; u < kU; ++u) v[u] = load_stream(p + (uint64_t)(rb + u) * half_w);
 #pragma unroll
       for (uint32_t u = 0; u < kU; ++u) {
         c0 += __popc(v[u].x) + __popc(v[u].y);
@@ -139,7 +139,7 @@ __global__ __launch_bounds__(kScanBlock) void k_column_zeros(Dims d, const uint4
       }
     }
     for (; rb < d.R; ++rb) {
-      const uint4 v = p[(uint64_t)rb * half_w];
+      const uint4 v = load_stream(p + (uint64_t)rb * half_w);
       c0 += __popc(v.x) + __popc(v.y);
       c1 += __popc(v.z) + __popc(v.w);
     }
@@ -203,7 +203,7 @@ __global__ __launch_bounds__(kScanBlock) void k_merge_scan(Dims d, MergeSrc src,
 #pragma unroll
         for (uint32_t u = 0; u < kU; ++u) {
           if (rb0 + u >= d.R) break;
-          const uint4 w = src.p[j][first + (uint64_t)(rb0 + u) * half_w];
+          const uint4 w = load_stream(src.p[j] + first + (uint64_t)(rb0 + u) * half_w);
           v[u].x |= w.x;
           v[u].y |= w.y;
           v[u].z |= w.z;
@@ -213,7 +213,7 @@ __global__ __launch_bounds__(kScanBlock) void k_merge_scan(Dims d, MergeSrc src,
 #pragma unroll
       for (uint32_t u = 0; u < kU; ++u) {
         if (rb0 + u >= d.R) break;
-        if (dst) dst[first + (uint64_t)(rb0 + u) * half_w] = v[u];
+        if (dst) store_stream(dst + first + (uint64_t)(rb0 + u) * half_w, v[u]);
         c0 += __popc(v[u].x) + __popc(v[u].y);
         c1 += __popc(v[u].z) + __popc(v[u].w);
       }

@@ -91,15 +91,15 @@ __global__ __launch_bounds__(kBlock) void k_merge_or(Dims d, uint4* dst, MergeSo
   }
   const uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
   for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n16; i += stride) {
-    uint4 v = accumulate ? dst[i] : make_uint4(0u, 0u, 0u, 0u);
+    uint4 v = accumulate ? load_stream(dst + i) : make_uint4(0u, 0u, 0u, 0u);
     for (int j = 0; j < k; ++j) {
-      const uint4 w = s.p[j][i];
+      const uint4 w = load_stream(s.p[j] + i);
       v.x |= w.x;
       v.y |= w.y;
       v.z |= w.z;
       v.w |= w.w;
     }
-    dst[i] = v;
+    store_stream(dst + i, v);
   }
 }
 
