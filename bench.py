@@ -43,9 +43,9 @@ HBM_PEAK_GBS = 8000.0
 # tuning), from FETCH_SIZE and WRITE_SIZE scaled by a 1 GiB copy's counters;
 # valid only while the update kernels' sources are the ones measured
 # (profiles/update_core_edge_64M_traffic.txt).
-UPDATE_TRAFFIC = {"bytes": 3445876620, "sources": {
+UPDATE_TRAFFIC = {"bytes": 3489068079, "sources": {
     "paper_1901_06207_amd/csrc/cbaa_partition.hip":
-        "ccecc820ae0583c17206ba85520c86c516773b8787eafaeb17c141eab7d76224",
+        "85a85f707621c25a17ad7191aa03dcc2a89e7858ea9bc5eb5702559ce78957ba",
     "paper_1901_06207_amd/csrc/cbaa_internal.hpp":
         "04742cfdeb7a9049a49c18455a2a890d340d8c3e9ea9799752d7d5507db85aca"}}
 

@@ -404,6 +404,15 @@ __global__ __launch_bounds__(kBlock) void k_fills(Batch b, const uint32_t* __res
   }
 }
 
+// The apply reads each record once and writes each fresh row block once:
+// both with the non-temporal hint (the scatter's run writes, by contrast,
+// need L2 to merge the runs of neighbouring chunks into whole lines).
+typedef uint32_t u32x2_nt __attribute__((ext_vector_type(2)));
+__device__ inline uint2 load_rec_nt(const uint2* p) {
+  const u32x2_nt v = __builtin_nontemporal_load((const u32x2_nt*)p);
+  return make_uint2(v.x, v.y);
+}
+
 __device__ inline uint32_t pack_rank(uint32_t rk, int u, uint32_t rank) {
   return rk | (rank << (16 * (u & 1)));
 }
@@ -653,7 +662,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* 
 #pragma unroll
       for (int u = 0; u < kApplyUnroll; ++u) {
         const uint32_t i = i0 + u * kBlock;
-        rr[u] = i < r1 ? rec[i] : make_uint2(0u, 0u);
+        rr[u] = i < r1 ? load_rec_nt(rec + i) : make_uint2(0u, 0u);
       }
 #pragma unroll
       for (int u = 0; u < kApplyUnroll; ++u) {
@@ -682,7 +691,7 @@ __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* 
       // sole writer of an empty row block: store it whole
       const uint4* t4 = (const uint4*)tile;
       uint4* d4 = (uint4*)dst;
-      for (uint32_t w = threadIdx.x; w < d.W / 2; w += kBlock) d4[w] = t4[w];
+      for (uint32_t w = threadIdx.x; w < d.W / 2; w += kBlock) store_stream(d4 + w, t4[w]);
     } else {
       for (uint32_t w = threadIdx.x; w < d.W; w += kBlock) {
         const uint64_t v = tile[w];
