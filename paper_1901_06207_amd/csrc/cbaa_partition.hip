@@ -46,7 +46,7 @@ namespace {
 constexpr int kBlock = 1024;
 constexpr uint32_t kMaxBins = 8192;      // bins of a stream (both cubes)
 constexpr int kUnroll = 8;                // independent loads in flight per thread
-constexpr int kApplyUnroll = 16;
+constexpr int kApplyUnroll = 8;           // record loads in flight per apply thread
 constexpr uint32_t kMaxTileWords = 16384; // 128 KiB LDS tile
 // Scatter blocks of 1024 threads (16 waves, 128 registers per lane): a chunk
 // of 16 pairs per thread stays in registers with no spill, and its 8-byte
@@ -655,7 +655,8 @@ __global__ __launch_bounds__(kBlock) void k_apply(Dims d, Batch b, const uint2* 
     const uint32_t r0 = (uint32_t)r0w;
     const uint32_t r1 = (uint32_t)(r0w + b.seg < end ? r0w + b.seg : end);
     const uint2* rec = rec_all + st.rec_base;
-    for (uint32_t w = threadIdx.x; w < d.W; w += kBlock) tile[w] = 0;
+    uint4* tile4 = (uint4*)tile;
+    for (uint32_t w = threadIdx.x; w < d.W / 2; w += kBlock) tile4[w] = make_uint4(0u, 0u, 0u, 0u);
     __syncthreads();
     for (uint32_t i0 = r0 + threadIdx.x; i0 < r1; i0 += kBlock * kApplyUnroll) {
       uint2 rr[kApplyUnroll];
