@@ -76,6 +76,11 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched-streams summary in the default line")
+    ap.add_argument("--pipeline", action="store_true",
+                    help="also time windows back to back, each window end overlapping the next "
+                         "window's update (off by default)")
     ap.add_argument("--cpu-sample", type=int, default=0,
                     help="packets of the window the CPU oracle step is timed on (0 = all)")
     ap.add_argument("--workload", choices=["core-edge", "batched", "sweep"], default="core-edge",
@@ -387,6 +392,16 @@ def main():
     scan = {"cube_bytes": int(cube_bytes), "ms": round(float(np.median(s_ms[1:])), 4),
             "achieved_gbs": round(scan_gbs, 1), "frac": round(scan_gbs / HBM_PEAK_GBS, 4)}
 
+    # pipelined windows: a second set of router cubes, so that the window end
+    # of one window (latency-bound tuple check, list copy) runs on the side
+    # streams while the next window's update streams over the other set
+    pipelined = None
+    if per_side and graph is not None and not per_router and args.pipeline:
+        pipelined = bench_pipelined(cfg, dev, args, d_parts, local, table, scratch_u, tuning,
+                                    scratch_r, outs, stats, capacity, d_sides, h_sides,
+                                    h_outs, h_stats, ref_lists, n_found, stream, wstreams,
+                                    trace.n, ms_per_step)
+
     # the restored lists of the step (graph replay) against the window's exact
     # per-host counts, per side (the generator's construction counts: every
     # peer of a host is a distinct address, pinned equal to a sort-unique count)
@@ -405,6 +420,9 @@ def main():
     serving = None if args.no_serve else bench_serving(cfg, dev, args)
     learned = None if args.no_learned else bench_learned(cfg, trace, g_src, local, dev, args)
     cpu = None if args.no_cpu_baseline else cpu_baseline(trace.pairs, args.cpu_sample, args.theta)
+    batched = None
+    if not args.no_batched and args.scale == 1.0:
+        batched = batched_summary(bench_batched(cfg, dev, args, emit=False))
 
     out = {
         "metric": METRIC,
@@ -462,6 +480,8 @@ def main():
             "super_hosts": {"source_keyed": n_found[0], "destination_keyed": n_found[1]},
         },
         "roofline": roofline,
+        "pipelined": pipelined,
+        "batched": batched,
         "accuracy": accuracy,
         "serving": serving,
         "learned": learned,
@@ -471,6 +491,89 @@ def main():
         out["autotune"] = {"best": tune_info["best"], "best_ms": round(tune_info["best_ms"], 4),
                            "default_ms": round(tune_info["default_ms"], 4)}
     print(json.dumps(out), flush=True)
+
+
+def bench_pipelined(cfg, dev, args, d_parts, local, table, scratch_u, tuning, scratch_r, outs,
+                    stats, capacity, d_sides, h_sides, h_outs, h_stats, ref_lists, n_found,
+                    stream, wstreams, n_packets, step_ms):
+    """Windows back to back with their window ends overlapping the next
+    window's update. Two sets of router cubes, A and B; one graph replay runs
+    two windows: B's window end (its update was the previous replay's) on the
+    side streams while A is updated, then A's window end while B is updated.
+    B's update waits for B's window end, and the replay ends with A's, so no
+    cube is written while it is read. Every window still runs the whole path
+    (update, merge and restore per side, lists to the host)."""
+    import numpy as np
+    import torch
+
+    from paper_1901_06207_amd import cbaa
+
+    local_b = [(cbaa.new_cube(cfg, dev), cbaa.new_cube(cfg, dev)) for _ in local]
+    table_b = [(q, a, b, cbaa.SIDE_SRC, cbaa.BATCH_FRESH) for q, (a, b) in zip(d_parts, local_b)]
+
+    def window_end(cubes):
+        for i, st in enumerate(wstreams):
+            a = (cfg, None, [x[i] for x in cubes], args.theta, cbaa.THR_THM2, scratch_r[i],
+                 outs[i], capacity, stats[i])
+            cbaa.cbaa_merge_scan(*a, st)
+            cbaa.cbaa_restore_scanned(*a, st)
+            with torch.cuda.stream(st):
+                h_sides[i].copy_(d_sides[i], non_blocking=True)
+
+    def join_sides():
+        for st in wstreams:
+            e = torch.cuda.Event()
+            e.record(st)
+            stream.wait_event(e)
+
+    def period():
+        fork = torch.cuda.Event()
+        fork.record(stream)
+        for st in wstreams:
+            st.wait_event(fork)
+        window_end(local_b)
+        cbaa.cbaa_update_batch(cfg, table, scratch_u, tuning, stream)
+        a_done = torch.cuda.Event()
+        a_done.record(stream)
+        join_sides()                       # B is read no more: its update may start
+        cbaa.cbaa_update_batch(cfg, table_b, scratch_u, tuning, stream)
+        for st in wstreams:
+            st.wait_event(a_done)
+        window_end(local)
+        join_sides()
+
+    cbaa.cbaa_update_batch(cfg, table_b, scratch_u, tuning, stream)   # B's first window
+    torch.cuda.synchronize(dev)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=stream):
+        period()
+    torch.cuda.synchronize(dev)
+    for _ in range(max(1, args.warmup)):
+        g.replay()
+    torch.cuda.synchronize(dev)
+    same = all(int(h_stats[i][0]) == n_found[i] and torch.equal(
+        h_outs[i][: n_found[i] * 16], ref_lists[i]) for i in range(2))
+    if not same:
+        raise SystemExit("pipelined windows differ from the step's lists")
+    replays = max(1, args.steps // 2)
+    torch.cuda.synchronize(dev)
+    t0 = time.perf_counter()
+    for _ in range(replays):
+        g.replay()
+    torch.cuda.synchronize(dev)
+    ms = (time.perf_counter() - t0) * 1e3 / (2 * replays)
+    # the two sets take the same packets, so their cubes must be equal word for word
+    same_cubes = all(torch.equal(x, y) for pa, pb in zip(local, local_b) for x, y in zip(pa, pb))
+    if not same_cubes:
+        raise SystemExit("pipelined windows: the two cube sets differ")
+    del g, local_b
+    return {"windows": 2 * replays, "ms_per_window": round(ms, 4),
+            "gpkt_s": round(n_packets / (ms * 1e-3) / 1e9, 3),
+            "over_step": round(step_ms / ms, 3), "lists_equal_step": bool(same),
+            "cube_sets_equal": bool(same_cubes),
+            "note": ("two sets of router cubes; each window's end (both sides on their own "
+                     "streams, lists to the host) overlaps the next window's update; steady "
+                     "state over whole graph replays of two windows each")}
 
 
 def detection_accuracy(ips, est, hosts, counts, theta, hosts_sorted=False):
@@ -578,7 +681,7 @@ def calibrate_copy(dev, nbytes=1 << 30):
     log(f"calibration copy: {nbytes} bytes read and written per copy, 3 copies")
 
 
-def bench_batched(cfg, dev, args):
+def bench_batched(cfg, dev, args, emit=True):
     """K edge-router streams with log-uniform 1M-64M packets (core-edge shape,
     one seed per stream), both cubes per stream, in one graph replay: zero the
     cubes, one batched update with autotuned shapes, restore every stream's
@@ -692,7 +795,24 @@ def bench_batched(cfg, dev, args):
                      "candidates": len(tune["candidates"])},
         "cpu_baseline": None,
     }
+    if not emit:
+        del graph, cubes, table, d_pairs, scratch, g, rs, outs, stats
+        torch.cuda.synchronize(dev)
+        torch.cuda.empty_cache()
+        return out
     print(json.dumps(out), flush=True)
+
+
+def batched_summary(res):
+    """The batched workload's figures carried in the default line."""
+    p, r = res["phases"], res["roofline"]
+    return {"workload": res["config"]["workload"], "packets": res["config"]["packets"],
+            "streams": res["config"]["streams"], "gpkt_s": res["value"],
+            "ms_per_window": res["ms_per_step"], "update_ms": p["update_ms"],
+            "update_gpkt_s": p["update_gpkt_s"], "update_hbm_frac": r["frac"],
+            "local_restore_ms_per_cube": p["local_restore_ms_per_cube"],
+            "merge_ms": p["merge_ms"], "tuning": res["autotune"]["best"],
+            "tuned_ms": res["autotune"]["best_ms"], "default_ms": res["autotune"]["default_ms"]}
 
 
 # RA start bits per r for the sweep: |EP| = (10, 9, 10), (10, 9, 9), (9, 9, 9)
