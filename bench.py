@@ -325,6 +325,9 @@ def main():
         mark("w1", stream)
     torch.cuda.synchronize(dev)
     window_end_other_ms = span("w0", "w1") / 2.0
+    mall = mall_cold_warm(cfg, dev, args, stream, table, scratch_u, tuning, local, scratch_r,
+                          outs, stats, capacity, phase_steps)
+    pcie = host_fed(dev, stream, graph, parts, d_parts, trace.n, phase_steps, ms_per_step)
     upd_gpkts = trace.n / (upd_ms.mean() * 1e-3) / 1e9
 
     # roofline of the dominant kernel set, the batched update call: algorithmic
@@ -478,6 +481,8 @@ def main():
                 "frac": round((len(parts) + (1 if args.store_merged else 0)) * cube_bytes
                               / (float(window_end_ms.mean()) * 1e-3) / 1e9 / HBM_PEAK_GBS, 4)},
             "super_hosts": {"source_keyed": n_found[0], "destination_keyed": n_found[1]},
+            "mall": mall,
+            "host_fed": pcie,
         },
         "roofline": roofline,
         "pipelined": pipelined,
@@ -491,6 +496,87 @@ def main():
         out["autotune"] = {"best": tune_info["best"], "best_ms": round(tune_info["best_ms"], 4),
                            "default_ms": round(tune_info["default_ms"], 4)}
     print(json.dumps(out), flush=True)
+
+
+def mall_cold_warm(cfg, dev, args, stream, table, scratch_u, tuning, local, scratch_r, outs,
+                   stats, capacity, reps):
+    """The update call and one side's window end, cold and warm in the 256 MB
+    MALL (Infinity Cache): a cold run follows a 512 MiB device write that
+    evicts it, a warm run repeats the same call at once."""
+    import numpy as np
+    import torch
+
+    from paper_1901_06207_amd import cbaa
+
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    side = (cfg, None, [x[0] for x in local], args.theta, cbaa.THR_THM2, scratch_r[0], outs[0],
+            capacity, stats[0])
+    calls = {"update": lambda: cbaa.cbaa_update_batch(cfg, table, scratch_u, tuning, stream),
+             "window_end_source_side": lambda: cbaa.cbaa_merge_restore(*side, stream)}
+    res = {}
+    for name, fn in calls.items():
+        cold, warm = [], []
+        for _ in range(reps):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+            with torch.cuda.stream(stream):
+                flush.fill_(1)
+            ev[0].record(stream)
+            fn()
+            ev[1].record(stream)
+            fn()
+            ev[2].record(stream)
+            ev[2].synchronize()
+            cold.append(ev[0].elapsed_time(ev[1]))
+            warm.append(ev[1].elapsed_time(ev[2]))
+        res[name] = {"cold_ms": round(float(np.median(cold)), 4),
+                     "warm_ms": round(float(np.median(warm)), 4)}
+    del flush
+    res["note"] = "cold: after a 512 MiB device write; warm: the same call repeated at once; medians"
+    return res
+
+
+def host_fed(dev, stream, graph, parts, d_parts, n_packets, reps, step_ms):
+    """The window's pairs from pinned host memory: the copy alone, and the
+    step with the next window's copy running beside it on a copy stream
+    (double buffering; the copy lands in a spare buffer of the same size)."""
+    import numpy as np
+    import torch
+
+    h = [torch.from_numpy(np.ascontiguousarray(q, dtype=np.uint32).view(np.int32)).pin_memory()
+         for q in parts]
+    spare = [torch.empty_like(d) for d in d_parts]
+    cstream = torch.cuda.Stream(device=dev)
+    t = []
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(cstream)
+        with torch.cuda.stream(cstream):
+            for src, dst in zip(h, spare):
+                dst.copy_(src, non_blocking=True)
+        e1.record(cstream)
+        e1.synchronize()
+        t.append(e0.elapsed_time(e1))
+    h2d_ms = float(np.median(t))
+    nbytes = sum(int(x.numel()) * 4 for x in h)
+    out = {"h2d_ms": round(h2d_ms, 4), "h2d_gbs": round(nbytes / (h2d_ms * 1e-3) / 1e9, 1),
+           "serial_gpkt_s": round(n_packets / ((h2d_ms + step_ms) * 1e-3) / 1e9, 3),
+           "overlapped_gpkt_s": None}
+    if graph is not None:
+        torch.cuda.synchronize(dev)
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            with torch.cuda.stream(cstream):
+                for src, dst in zip(h, spare):
+                    dst.copy_(src, non_blocking=True)
+            graph.replay()
+            torch.cuda.synchronize(dev)
+        ms = (time.perf_counter() - t0) * 1e3 / reps
+        out["overlapped_ms_per_window"] = round(ms, 4)
+        out["overlapped_gpkt_s"] = round(n_packets / (ms * 1e-3) / 1e9, 3)
+    out["note"] = ("PCIe-inclusive rates: serial = copy then step (derived from the two times), "
+                   "overlapped = the next window's copy beside the step (measured)")
+    del spare, h
+    return out
 
 
 def bench_pipelined(cfg, dev, args, d_parts, local, table, scratch_u, tuning, scratch_r, outs,
