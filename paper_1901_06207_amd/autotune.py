@@ -2,8 +2,10 @@
 
 Times ``cbaa_update_batch`` on the caller's own streams with HIP events for a
 few shapes, one parameter at a time (coordinate descent over the sample's
-piece size, apply segment size, apply grid), and returns the fastest. Results are cached per
-(configuration, number of streams, total packets rounded to a power of two).
+piece size, apply segment size, apply grid, five values each, repeated while a
+sweep still moves the best shape, at most ``rounds`` sweeps), and returns the
+fastest. Results are cached per (configuration, number of streams, total
+packets rounded to a power of two).
 """
 
 from __future__ import annotations
@@ -14,9 +16,9 @@ import torch
 
 from . import cbaa
 
-CHUNKS = (4096, 16384, 65536)
-SEGS = (32768, 65536, 131072)
-APPLY_BLOCKS = (256, 512, 1024)
+CHUNKS = (4096, 8192, 16384, 32768, 65536)
+SEGS = (16384, 32768, 65536, 131072, 262144)
+APPLY_BLOCKS = (256, 512, 768, 1024, 2048)
 
 _cache: dict = {}
 
@@ -47,7 +49,8 @@ def _time(cfg, streams, tuning, scratch, repeats, stream):
     return ms[len(ms) // 2]
 
 
-def tune_update(cfg, streams, repeats: int = 3, use_cache: bool = True, stream=None) -> dict:
+def tune_update(cfg, streams, repeats: int = 3, use_cache: bool = True, stream=None,
+                rounds: int = 2) -> dict:
     """Returns {"best": tuning dict, "best_ms": t, "default_ms": t0,
     "candidates": [{"tuning": ..., "ms": ...}, ...]}. The cubes of the streams
     are overwritten."""
@@ -55,8 +58,9 @@ def tune_update(cfg, streams, repeats: int = 3, use_cache: bool = True, stream=N
     if use_cache and key in _cache:
         return _cache[key]
     stream = stream or torch.cuda.current_stream()
-    need = max(cbaa.cbaa_update_batch_scratch_bytes(cfg, streams, dict(chunk_pairs=c))
-               for c in CHUNKS)
+    need = max(cbaa.cbaa_update_batch_scratch_bytes(cfg, streams,
+                                                    dict(chunk_pairs=c, seg_records=g))
+               for c in CHUNKS for g in SEGS)
     scratch = cbaa.scratch_tensor(need, streams[0][1].device)
     best = dict(chunk_pairs=16384, seg_records=65536, apply_blocks=512)
     seen = {}
@@ -68,10 +72,14 @@ def tune_update(cfg, streams, repeats: int = 3, use_cache: bool = True, stream=N
         return seen[k]
 
     default_ms = measure(best)
-    for name, values in (("chunk_pairs", CHUNKS), ("seg_records", SEGS),
-                         ("apply_blocks", APPLY_BLOCKS)):
-        scores = {v: measure(dict(best, **{name: v})) for v in values}
-        best = dict(best, **{name: min(scores, key=scores.get)})
+    for _ in range(max(1, rounds)):
+        start = dict(best)
+        for name, values in (("chunk_pairs", CHUNKS), ("seg_records", SEGS),
+                             ("apply_blocks", APPLY_BLOCKS)):
+            scores = {v: measure(dict(best, **{name: v})) for v in values}
+            best = dict(best, **{name: min(scores, key=scores.get)})
+        if best == start:
+            break
     res = {"best": best, "best_ms": measure(best), "default_ms": default_ms,
            "candidates": [{"tuning": dict(chunk_pairs=k[0], seg_records=k[1], apply_blocks=k[2]),
                            "ms": v} for k, v in seen.items()]}

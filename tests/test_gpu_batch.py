@@ -62,7 +62,8 @@ def test_batch_uneven_streams_bitexact(cb, two):
 
 @pytest.mark.parametrize("tuning", [dict(chunk_pairs=16384), dict(chunk_pairs=131072, seg_records=8192),
                                     dict(apply_blocks=37), dict(chunk_pairs=1024, seg_records=1024,
-                                                                apply_blocks=2048)])
+                                                                apply_blocks=2048),
+                                    dict(chunk_pairs=32768, seg_records=262144, apply_blocks=768)])
 def test_batch_tunings_and_shared_cube(cb, tuning):
     """Every tile/partition shape gives the same cube; two streams that share
     a cube give the cube of their union."""
