@@ -77,7 +77,8 @@ def tune_update(cfg, streams, repeats: int = 3, use_cache: bool = True, stream=N
         for name, values in (("chunk_pairs", CHUNKS), ("seg_records", SEGS),
                              ("apply_blocks", APPLY_BLOCKS)):
             scores = {v: measure(dict(best, **{name: v})) for v in values}
-            best = dict(best, **{name: min(scores, key=scores.get)})
+            # a tie keeps the current value: the shape moves only for a gain
+            best = dict(best, **{name: min(scores, key=lambda v: (scores[v], v != best[name]))})
         if best == start:
             break
     res = {"best": best, "best_ms": measure(best), "default_ms": default_ms,
